@@ -1,0 +1,466 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage it checks. None of them retypes the oracle's formula: they use
+values printed in the paper (tests/golden/paper_tables.json), closed forms, invariants,
+exact sum rules evaluated by brute force, and convergence orders.
+"""
+import json
+import math
+import os
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import stencil_algebra as sa
+from oracle import thermo
+from paper_2505_23647_amd import synth
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))
+CS2 = 1.0 / 3.0
+
+
+def lin(form, **knobs):
+    """Evaluate a {term: coefficient} linear form of the golden tables."""
+    tot = Fr(0)
+    for k, v in form.items():
+        tot += Fr(v) * (Fr(1) if k == "1" else Fr(knobs[k]))
+    return tot
+
+
+def table_weights(rows, **knobs):
+    return {int(code): lin(form, **knobs) for code, form in rows.items()}
+
+
+# --------------------------------------------------------------------------- velocity sets
+@pytest.mark.parametrize("d,Q", [(2, 9), (3, 19)])
+def test_velocity_set_isotropy(d, Q):
+    """Sec. Lattice Boltzmann: <1>_w = 1, <xi xi>_w = c_s^2 delta, <xi^4>_w = c_s^4 Delta."""
+    xi, w = oracle.velset(d)
+    assert len(w) == Q
+    assert abs(w.sum() - 1) < 1e-15
+    xi = xi[:, :d].astype(float)
+    m2 = np.einsum("i,ia,ib->ab", w, xi, xi)
+    assert np.allclose(m2, CS2 * np.eye(d), atol=1e-15)
+    m4 = np.einsum("i,ia,ib,ic,id->abcd", w, xi, xi, xi, xi)
+    dl = np.eye(d)
+    Delta = (np.einsum("ab,cd->abcd", dl, dl) + np.einsum("ac,bd->abcd", dl, dl)
+             + np.einsum("ad,bc->abcd", dl, dl))
+    assert np.allclose(m4, CS2 ** 2 * Delta, atol=1e-15)
+    # odd moments vanish
+    assert np.allclose(np.einsum("i,ia->a", w, xi), 0, atol=1e-16)
+    assert np.allclose(np.einsum("i,ia,ib,ic->abc", w, xi, xi, xi), 0, atol=1e-16)
+
+
+# --------------------------------------------------------------------------- stencil groups
+GROUPS2 = {1: 4, 2: 4, 4: 4, 5: 8, 8: 4, 9: 4, 16: 4, 18: 4}
+GROUPS3 = {1: 6, 2: 12, 3: 8, 4: 6, 5: 24, 6: 24, 8: 12, 9: 24, 1009: 6, 16: 6, 18: 12}
+
+
+@pytest.mark.parametrize("d,groups", [(2, GROUPS2), (3, GROUPS3)])
+def test_shell_groups(d, groups):
+    """Fig. 1 / Sec. sigma_1 tuning: group sizes; the C++ and Python enumerations agree."""
+    for code, size in groups.items():
+        vs = sa.vectors(d, code)
+        assert len(vs) == size, code
+        e, sh = oracle.stencil(d, [code])
+        assert sorted(map(tuple, e[:, :d].tolist())) == sorted(vs)
+        assert all(sum(c * c for c in v) == (9 if code == 1009 else code) for v in vs)
+
+
+def test_stencil_sizes_match_printed_counts():
+    """tab:e2n_values / tab:e4_tuning_6 / tab:e4e6_tuning_8: vector counts N_e."""
+    assert len(oracle.stencil(2, [1, 2])[0]) == GOLD["tab_e2n_values"]["E4"]["Ne2"]
+    assert len(oracle.stencil(2, [1, 2, 4])[0]) == GOLD["tab_e2n_values"]["E6"]["Ne2"]
+    assert len(oracle.stencil(2, [1, 2, 4, 5, 8])[0]) == GOLD["tab_e2n_values"]["E8"]["Ne2"]
+    assert len(oracle.stencil(3, [1, 2])[0]) == GOLD["tab_e2n_values"]["E4"]["Ne3"]
+    assert len(oracle.stencil(3, [1, 2, 3, 4])[0]) == GOLD["tab_e2n_values"]["E6"]["Ne3"]
+    assert len(oracle.stencil(3, [1, 2, 3, 4, 5, 6, 8])[0]) == GOLD["tab_e2n_values"]["E8"]["Ne3"]
+    assert len(oracle.stencil(2, [1, 2, 4, 8])[0]) == GOLD["tab_e4_tuning_6"]["Ne"]["d2"]
+    assert len(oracle.stencil(3, [1, 2, 3, 4, 8])[0]) == GOLD["tab_e4_tuning_6"]["Ne"]["d3"]
+    assert len(oracle.stencil(2, [1, 2, 4, 5, 8, 9, 18])[0]) == GOLD["tab_e4e6_tuning_8"]["Ne"]["d2"]
+    assert len(oracle.stencil(3, [1, 2, 3, 4, 5, 6, 8, 9, 1009, 16, 18])[0]) == \
+        GOLD["tab_e4e6_tuning_8"]["Ne"]["d3"]
+
+
+# --------------------------------------------------------------------------- tab:defe2nI2n
+@pytest.mark.parametrize("d", [2, 3])
+def test_isotropy_coefficient_table(d):
+    """tab:defe2nI2n rows equal the brute-force moment conditions, shell by shell."""
+    rows = GOLD["tab_defe2nI2n"][f"d{d}"]
+    shells = [1, 2, 4, 5, 8, 9, 16, 18] if d == 2 else [1, 2, 3, 4, 5, 6, 8, 9, 1009, 16, 18]
+    for name, form in rows.items():
+        for code in shells:
+            if d == 2 and name.startswith("I") and code == 16:
+                continue  # printed 2D anisotropy rows leave W(16) out (table note)
+            got = sa.coefficients(d, {code: 1})[name]
+            want = Fr(form.get(str(code), "0"))
+            assert got == want, (name, code, got, want)
+
+
+# --------------------------------------------------------------------------- tab:e2n_values
+@pytest.mark.parametrize("d,name,W", [
+    (2, "E4", {1: Fr(1, 3), 2: Fr(1, 12)}),
+    (2, "E6", {1: Fr(4, 15), 2: Fr(1, 10), 4: Fr(1, 120)}),
+    (2, "E8", {1: Fr(4, 21), 2: Fr(4, 45), 4: Fr(1, 60), 5: Fr(2, 315), 8: Fr(1, 5040)}),
+    (3, "E4", {1: Fr(1, 6), 2: Fr(1, 12)}),
+    (3, "E6", {1: Fr(2, 15), 2: Fr(1, 15), 3: Fr(1, 60), 4: Fr(1, 120)}),
+    (3, "E8", {1: Fr(4, 45), 2: Fr(1, 21), 3: Fr(2, 105), 4: Fr(5, 504), 5: Fr(1, 315), 6: Fr(1, 630),
+               8: Fr(1, 5040)}),
+])
+def test_maximally_isotropic_constants(d, name, W):
+    """tab:e2n_values: e4, e6, e8 of the maximally isotropic stencils; e2 = 1 and the
+    anisotropy conditions of the stencil's order vanish."""
+    c = sa.coefficients(d, W)
+    ref = GOLD["tab_e2n_values"][name]
+    assert c["e2"] == 1
+    # above the isotropy order e_2n is read in the xy plane (eq. wproj keeps those moments)
+    c2 = sa.coefficients(2, sa.project_3d_to_2d(W)) if d == 3 else c
+    assert c2["e4"] == Fr(ref["e4"]) and c2["e6"] == Fr(ref["e6"]) and c2["e8"] == Fr(ref["e8"])
+    order = int(name[1:])
+    for k in ("e4", "e6", "e8"):
+        if int(k[1:]) <= order:
+            assert c[k] == Fr(ref[k]), k
+    for k, v in c.items():
+        if k.startswith("I") and int(k[1:-1]) <= order:
+            assert v == 0, (k, v)
+
+
+def test_e4_weights_from_appendix():
+    """app:e4ex: W(1) = (2e2 + I40)/6, W(2) = (e2 - I40)/12 gives 1/3, 1/12 at e2=1, I40=0."""
+    W = sa.solve(2, [1, 2], {"e2": 1, "I40": 0})
+    ref = GOLD["weights_E4_2d"]
+    assert W == {1: Fr(ref["1"]), 2: Fr(ref["2"])}
+
+
+def test_family2d_reproduces_E8():
+    """app:MBMR E(8) weights = the e2=1, I40=I60=0 family at e4 = 4/7, e8 = 16/105."""
+    W = sa.family2d(Fr(4, 7), Fr(16, 105))
+    ref = GOLD["weights_E8_2d"]
+    assert W == {int(k): Fr(v) for k, v in ref.items() if k != "_cite"}
+
+
+def test_family3d_reproduces_E8_3d():
+    W = sa.family3d(Fr(4, 7), Fr(16, 105), Fr(1, 630))
+    assert W == {1: Fr(4, 45), 2: Fr(1, 21), 3: Fr(2, 105), 4: Fr(5, 504), 5: Fr(1, 315), 6: Fr(1, 630),
+                 8: Fr(1, 5040)}
+    c = sa.coefficients(3, W)
+    assert c["e8"] == Fr(16, 105) and c["e6"] == Fr(32, 105)
+
+
+# --------------------------------------------------------------------------- tuning tables
+KNOB_SAMPLES = [(Fr(-1, 6), Fr(1, 72), Fr(1, 6)), (Fr(-2, 5), Fr(3, 50), Fr(3, 10)),
+                (Fr(-1, 3), Fr(1, 20), Fr(7, 25))]
+
+
+@pytest.mark.parametrize("s0,s1,d0", KNOB_SAMPLES)
+def test_table_e4_tuning_6(s0, s1, d0):
+    """tab:e4_tuning_6: e2 = 1, e4 = -2 sigma0, 6th-order isotropy, and d=3 projects onto d=2."""
+    g = GOLD["tab_e4_tuning_6"]
+    W2 = table_weights(g["d2"], s0=s0)
+    W3 = table_weights(g["d3"], s0=s0)
+    c2, c3 = sa.coefficients(2, W2), sa.coefficients(3, W3)
+    for c in (c2, c3):
+        assert c["e2"] == 1 and c["e4"] == -2 * s0 and c["I40"] == 0 and c["I60"] == 0
+    assert c3["I61"] == 0
+    assert sa.project_3d_to_2d(W3) == {k: v for k, v in W2.items() if v != 0}
+    assert sa.knobs(list(W2), W2)["sigma0"] == s0
+
+
+@pytest.mark.parametrize("s0,s1,d0", KNOB_SAMPLES)
+def test_table_e4e6_tuning_8(s0, s1, d0):
+    """tab:e4e6_tuning_8 and eq. hatsigma01eI: e4 = -2 sigma0, e6 = 4 sigma1, 8th-order
+    isotropy, and the pressure-tensor knobs return sigma0, sigma1 (3D through eq. wproj)."""
+    g = GOLD["tab_e4e6_tuning_8"]
+    W2 = table_weights(g["d2"], s0=s0, s1=s1)
+    W3 = table_weights(g["d3"], s0=s0, s1=s1)
+    c2, c3 = sa.coefficients(2, W2), sa.coefficients(3, W3)
+    for c in (c2, c3):
+        assert c["e2"] == 1 and c["e4"] == -2 * s0 and c["e6"] == 4 * s1
+    for k in ("I40", "I60", "I80", "I81"):
+        assert c2[k] == 0, k
+    for k in ("I40", "I60", "I61", "I80", "I81", "I82"):
+        assert c3[k] == 0, k
+    k2 = sa.knobs(list(W2), W2)
+    assert (k2["sigma0"], k2["sigma1"]) == (s0, s1)
+    P3 = sa.project_3d_to_2d(W3)
+    k3 = sa.knobs(list(P3), P3)
+    assert (k3["sigma0"], k3["sigma1"]) == (s0, s1)
+
+
+@pytest.mark.parametrize("s0,s1,d0", KNOB_SAMPLES)
+def test_tables_tolman_tuning(s0, s1, d0):
+    """tab:e4e6e8_tuning_6_2d / _3d: all three knobs recovered, 6th-order isotropy, e2 = 1."""
+    W2 = table_weights(GOLD["tab_e4e6e8_tuning_6_2d"]["d2"], s0=s0, s1=s1, d0=d0)
+    W3 = table_weights(GOLD["tab_e4e6e8_tuning_6_3d"]["d3"], s0=s0, s1=s1, d0=d0)
+    c2, c3 = sa.coefficients(2, W2), sa.coefficients(3, W3)
+    assert c2["e2"] == 1 and c2["I40"] == 0 and c2["I60"] == 0
+    assert c3["e2"] == 1 and c3["I40"] == 0 and c3["I60"] == 0 and c3["I61"] == 0
+    k2 = sa.knobs(list(W2), W2)
+    assert (k2["sigma0"], k2["sigma1"], k2["delta0"]) == (s0, s1, d0)
+    P3 = sa.project_3d_to_2d(W3)
+    k3 = sa.knobs(list(P3), P3)
+    assert (k3["sigma0"], k3["sigma1"], k3["delta0"]) == (s0, s1, d0)
+    # eq. hatdelta0eI holds identically on this family
+    assert d0 == Fr(1, 12) + Fr(95, 432) * c2["e4"] + Fr(7, 72) * c2["e6"] - Fr(5, 144) * c2["e8"]
+
+
+def test_hatdelta0_reference_value():
+    """Sec. Nucleation Rates: delta0(e4=4/5, e6=e4^(3/2), e8=e4^2) = 7 sqrt5/225 + 32/135."""
+    e4 = 0.8
+    d0 = 1 / 12 + 95 * e4 / 432 + 7 * e4 ** 1.5 / 72 - 5 * e4 ** 2 / 144
+    assert abs(d0 - (7 * math.sqrt(5) / 225 + 32 / 135)) < 1e-15
+    assert round(d0, 3) == GOLD["hatdelta0_reference"]["value"]
+    assert float(sa.epsilon(Fr(4, 5))) == 14 / 29
+
+
+def test_projected_pressure_tensor_table():
+    """tab:pnptcoeffs: the 1D projection of the d=2 lattice pressure tensor, shell by shell,
+    and the symmetry eq. (1dPNT) assumes (psi(x)psi(x+k) and psi(x)psi(x-k) share a_k)."""
+    for comp in ("N", "T"):
+        ref = GOLD["tab_pnptcoeffs"][comp]
+        for code in (1, 2, 4, 5, 8, 9, 16, 18):
+            got = sa.eq1dpnt_coefficients([code], {code: 1}, comp)
+            for name, form in ref.items():
+                if not name.startswith("_"):
+                    assert got[name] == Fr(form.get(str(code), "0")), (comp, code, name)
+            for k in ("a4", "a3", "a2", "a1"):
+                assert got["_" + k + "m"] == got[k]
+            assert got["_b13m"] == got["b13"] and got["_b12m"] == got["b12"]
+
+
+def test_taylor_coefficients_table():
+    """tab:pn_minus_ptcoeffs: c_mn from expanding the projected tensor; the zeroth and odd
+    orders cancel."""
+    ref = GOLD["tab_pn_minus_ptcoeffs"]
+    for code in (1, 2, 4, 5, 8, 9, 16, 18):
+        c = sa.taylor_c([code], {code: 1})
+        for name, form in ref.items():
+            if name.startswith("_"):
+                continue
+            m, n = int(name[1]), int(name[2])
+            assert c[(m, n)] == Fr(form.get(str(code), "0")), (code, name)
+        assert c[(0, 0)] == 0 and c[(0, 1)] == 0 and c[(0, 3)] == 0 and c[(1, 2)] == 0
+
+
+def test_sigma0_knob_is_minus_half_e4():
+    """eq. hat_sigma_0_moments: c11 - c02 = -I40/4 - e4/2 for any weights."""
+    rng = np.random.default_rng(11)
+    for _ in range(5):
+        W = {c: Fr(int(v), 97) for c, v in zip([1, 2, 4, 5, 8, 9, 18], rng.integers(-50, 50, 7))}
+        c = sa.coefficients(2, W)
+        assert sa.knobs(list(W), W)["sigma0"] == -c["I40"] / 4 - c["e4"] / 2
+
+
+# --------------------------------------------------------------------------- thermodynamics
+def test_critical_coupling_exp():
+    """Sec. sigma_1 tuning: G_c = -e^2 for psi = exp(-1/n)."""
+    nc, Gc = thermo.critical(0)
+    assert abs(Gc + math.e ** 2) < 1e-12 and abs(nc - 1) < 1e-6
+
+
+def test_critical_coupling_eps():
+    """Sec. Tolman tuning: printed G_c for eps = 14/29 (no c_s^2 in that convention)."""
+    g = GOLD["critical_eps"]
+    printed = -g["num"] * g["root_arg"] ** (1 / 7) / g["den"]
+    _, Gc = thermo.critical(1, 14 / 29)
+    assert abs(Gc * CS2 - printed) < 1e-12
+
+
+def test_nucleation_setup_densities():
+    """Sec. Nucleation Rates: n_l ~ 1.264, liquid spinodal ~ 1.026, n_init(0.02) ~ 1.031."""
+    g = GOLD["nucleation"]
+    eps = 14 / 29
+    G = thermo.G_for_reduced_temperature(g["dT"], 1, eps)
+    ng, nl, _ = thermo.coexistence(G, 1, eps)
+    lo, hi = thermo.spinodal(G, 1, eps)
+    ninit = hi * (1 - g["a"]) + g["a"] * nl
+    # the paper quotes three decimals with "~" (1.0266 is printed as 1.026): agree to 1e-3
+    assert abs(nl - g["n_l"]) < 1e-3 and abs(hi - g["n_sl"]) < 1e-3 and abs(ninit - g["n_init"]) < 1e-3
+
+
+def test_maxwell_rule_is_chemical_equilibrium():
+    """eq. SCMaxwell with eps = 0 is equal area in (ln psi, P): check on a dense trapezoid."""
+    G = thermo.G_for_reduced_temperature(0.2)
+    ng, nl, p0 = thermo.coexistence(G)
+    n = np.linspace(ng, nl, 200001)
+    P = n * CS2 + 0.5 * G * CS2 * np.exp(-2 / n)
+    lnpsi = -1 / n
+    assert abs(np.trapezoid(p0 - P, lnpsi)) < 1e-9
+    assert abs(thermo.bulk_pressure(ng, G) - p0) < 1e-14 and abs(thermo.bulk_pressure(nl, G) - p0) < 1e-14
+
+
+# --------------------------------------------------------------------------- dynamics
+def _setup_droplet(L=64, R=12.0, dT=0.2, codes=(1, 2), W=(1 / 3, 1 / 12), tau=1.0, noise=0.0):
+    G = thermo.G_for_reduced_temperature(dT)
+    ng, nl, _ = thermo.coexistence(G)
+    n0 = synth.droplet((L, L), R, nl, ng, noise=noise, seed=0)
+    return oracle.Sim((L, L), tau, G, list(codes), list(W)).init_density(n0), G, ng, nl
+
+
+def test_post_collision_moments_closed_form():
+    """eqs. f_eq, GuoForcing, u^(eq): the post-collision populations at each site have
+    sum = n, first moment = j + F (for any tau: n u + (1 - 1/2tau) F with u = (j + F/2)/n
+    and tau = 1 gives j + F), second moment = n c^2 delta + n u u + (1 - 1/2tau)(uF + Fu)
+    when tau = 1 (f* = feq + S)."""
+    s, G, ng, nl = _setup_droplet(L=32, R=8.0, noise=1e-2)
+    s.run(7)
+    fl = s.fields()
+    f_before = s.f.copy()
+    s.run(1)
+    # undo the streaming: f*_i(x) = f_i(x + xi_i, t+1)
+    fstar = np.empty_like(s.f)
+    for i, (cx, cy, _) in enumerate(s.xi):
+        fstar[i] = np.roll(s.f[i].reshape(32, 32), shift=(-cy, -cx), axis=(0, 1)).reshape(-1)
+    xi = s.xi[:, :2].astype(float)
+    n, j, F, u = fl["n"], fl["j"][:, :2], fl["F"][:, :2], fl["u"][:, :2]
+    assert np.abs(fstar.sum(0) - n).max() < 1e-13
+    assert np.abs(np.einsum("iN,ia->Na", fstar, xi) - (j + F)).max() < 1e-13
+    m2 = np.einsum("iN,ia,ib->Nab", fstar, xi, xi)
+    want = (n[:, None, None] * CS2 * np.eye(2) + n[:, None, None] * np.einsum("Na,Nb->Nab", u, u)
+            + 0.5 * (np.einsum("Na,Nb->Nab", u, F) + np.einsum("Na,Nb->Nab", F, u)))
+    assert np.abs(m2 - want).max() < 1e-13
+    assert np.abs(F).max() > 1e-4  # the force is really acting
+    assert f_before.shape == s.f.shape
+
+
+def test_mass_and_momentum_conservation():
+    """Sec. Lattice Boltzmann: the collision conserves mass and momentum; the Shan-Chen force
+    sums to zero over a periodic domain, so the total physical momentum is conserved."""
+    s, *_ = _setup_droplet(L=48, R=10.0, noise=1e-3)
+    M0 = s.f.sum()
+    fl0 = s.fields()
+    P0 = (fl0["j"] + 0.5 * fl0["F"]).sum(0)
+    assert s.run(300) == 0
+    fl = s.fields()
+    assert abs(s.f.sum() / M0 - 1) < 1e-13
+    assert np.abs(fl["F"].sum(0)).max() < 1e-13
+    assert np.abs((fl["j"] + 0.5 * fl["F"]).sum(0) - P0).max() < 1e-12
+
+
+def test_uniform_state_is_invariant():
+    s = oracle.Sim((16, 12), 0.8, -8.0, [1, 2, 4, 5, 8],
+                   [float(v) for v in sa.family2d(Fr(1, 2), Fr(1, 8)).values()])
+    s.init_density(np.full(16 * 12, 1.3))
+    f0 = s.f.copy()
+    s.run(50)
+    assert np.abs(s.f - f0).max() < 1e-14
+
+
+def test_force_leading_order_taylor():
+    """eq. FSCLeading: F = -grad(G c^2 e2 psi^2 / 2) + O(k^2) for a smooth field; the error
+    falls by ~4x when the wavelength doubles (second order)."""
+    G = -6.0
+    W = [float(v) for v in sa.family2d(Fr(1, 2), Fr(1, 10)).values()]
+    errs = []
+    for L in (64, 128, 256):
+        x = np.arange(L)
+        n_line = 1.0 + 0.2 * np.sin(2 * np.pi * x / L)
+        n0 = np.tile(n_line, (4, 1)).reshape(-1)
+        s = oracle.Sim((L, 4), 1.0, G, [1, 2, 4, 5, 8], W).init_density(n0)
+        F = s.fields()["F"][:, 0].reshape(4, L)[0]
+        k = 2 * np.pi / L
+        psi = np.exp(-1 / n_line)
+        dn = 0.2 * k * np.cos(k * x)
+        dpsi = psi / n_line ** 2 * dn
+        lead = -G * CS2 * psi * dpsi  # -d/dx (G c^2 psi^2 / 2) with e2 = 1
+        errs.append(np.abs(F - lead).max() / np.abs(lead).max())
+    assert errs[0] < 2e-2
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
+
+
+@pytest.mark.slow
+def test_flat_interface_mechanical_equilibrium():
+    """App. LPT d=2 / Sec. Interface Physics: at a converged flat interface the normal
+    component P_N is constant on every site to machine precision (E(8) weights use the
+    |e|^2 = 5 irregular pairs), and the bulk densities approach the eq. SCMaxwell values."""
+    G = thermo.G_for_reduced_temperature(0.2)
+    ng, nl, p0 = thermo.coexistence(G, e4=4 / 7)
+    W = [4 / 21, 4 / 45, 1 / 60, 2 / 315, 1 / 5040]
+    nx = 96
+    s = oracle.Sim((nx, 1), 1.0, G, [1, 2, 4, 5, 8], W).init_density(synth.slab(nx, nl, ng, 24.0))
+    assert s.run(30000) == 0
+    P = s.pressure_tensor()
+    PN = P[0]
+    assert PN.max() - PN.min() < 1e-12 * abs(PN.mean())
+    n = s.fields()["n"]
+    assert abs(n.max() - nl) / nl < 2e-3 and abs(n.min() - ng) / ng < 2e-3
+    # tangential component differs inside the interface (a surface tension exists)
+    assert (P[0] - P[1]).max() > 1e-3
+
+
+def test_pressure_tensor_bulk_limit():
+    """App. LPT d=2 (bulk remark): on a uniform field P = [n c^2 + G c^2 e2 psi^2 / 2] delta."""
+    W = [4 / 21, 4 / 45, 1 / 60, 2 / 315, 1 / 5040]
+    G = -8.0
+    s = oracle.Sim((12, 10), 1.0, G, [1, 2, 4, 5, 8], W).init_density(np.full(120, 1.7))
+    P = s.pressure_tensor()
+    want = 1.7 * CS2 + 0.5 * G * CS2 * math.exp(-2 / 1.7)
+    assert np.abs(P[0] - want).max() < 1e-14 and np.abs(P[1] - want).max() < 1e-14
+    assert np.abs(P[2]).max() < 1e-15
+
+
+@pytest.mark.slow
+def test_laplace_law_droplet():
+    """Sec. sigma_1 tuning (Laplace-law paragraph): Delta P R = sigma_0 (d=2) up to O(delta/R);
+    sigma_0 from a flat slab at the same coupling with eq. sigma0pnpt."""
+    G = thermo.G_for_reduced_temperature(0.2)
+    ng, nl, _ = thermo.coexistence(G)
+    nx = 96
+    slab = oracle.Sim((nx, 1), 1.0, G, [1, 2], [1 / 3, 1 / 12]).init_density(synth.slab(nx, nl, ng, 24.0))
+    slab.run(20000)
+    P = slab.pressure_tensor()
+    sigma0 = 0.5 * (P[0] - P[1]).sum()  # two interfaces
+    L = 128
+    s = oracle.Sim((L, L), 1.0, G, [1, 2], [1 / 3, 1 / 12]).init_density(
+        synth.droplet((L, L), 20.0, nl, ng, noise=1e-3, seed=0))
+    assert s.run(6000) == 0
+    dP, Cd, Rs, sig, Re, dl = s.droplet_observables((L // 2, L // 2))
+    assert abs(dP * Re / sigma0 - 1) < 0.1
+    assert abs(Re - 20.0) < 2.0
+    # eq. SigmaCExpansion at first order: sigma_s = sigma_0 (1 - delta / R_s) with the measured
+    # delta = R_e - R_s, and that delta within 20% of the flat estimate eq. SCTolmanFlat
+    # (delta0 = c02 = W(1)/2 = 1/6 for E(4)); the paper reports a roughly constant offset.
+    assert abs(sig / (sigma0 * (1 - dl / Rs)) - 1) < 0.02
+    d_sc = -(G * CS2) / (2 * sigma0) * (1 / 6) * (math.exp(-2 / nl) - math.exp(-2 / ng))
+    assert abs(dl / d_sc - 1) < 0.2
+
+
+def test_literal_config_blows_up():
+    """The literal nearest-neighbour droplet (G = -5 read with the c_s^2 of eq. sc_f, so above
+    G_c; rho 2.0 / 0.15) is not at equilibrium and the over-pressured droplet diverges."""
+    L = 128
+    n0 = synth.droplet((L, L), 20.0, 2.0, 0.15, noise=1e-3, seed=0)
+    s = oracle.Sim((L, L), 1.0, -15.0, [1, 2], [1 / 3, 1 / 12]).init_density(n0)
+    assert s.run(200) == 5
+
+
+def test_tangent_linear_matches_finite_differences():
+    """The dual-number run of the plain loop against central differences of the same loop."""
+    L, R = 32, 8.0
+    G = thermo.G_for_reduced_temperature(0.2)
+    ng, nl, _ = thermo.coexistence(G)
+    n0 = synth.droplet((L, L), R, nl, ng)
+    codes = [1, 2, 4, 5, 8]
+    W = np.array([float(v) for v in sa.family2d(Fr(1, 2), Fr(1, 10)).values()])
+    steps = 300
+    obs, jac = oracle.droplet_tangent_linear((L, L), 1.0, G, codes, W, n0, steps, (L // 2, L // 2))
+
+    def run(Wv, Gv):
+        s = oracle.Sim((L, L), 1.0, Gv, codes, Wv).init_density(n0)
+        s.run(steps)
+        return s.droplet_observables((L // 2, L // 2))
+
+    base = run(W, G)
+    assert np.allclose(base, obs, rtol=1e-10, atol=1e-12)  # dual arithmetic rounds differently
+    for q in range(len(codes) + 1):
+        h = 1e-5 * (max(abs(W[q]), 1e-2) if q < len(codes) else abs(G))
+        Wp, Wm, Gp, Gm = W.copy(), W.copy(), G, G
+        if q < len(codes):
+            Wp[q] += h; Wm[q] -= h
+        else:
+            Gp += h; Gm -= h
+        fd = (run(Wp, Gp) - run(Wm, Gm)) / (2 * h)
+        scale = np.abs(jac[:, q]).max()
+        assert np.abs(fd - jac[:, q]).max() < 1e-5 * scale + 1e-9, q
