@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Throughput of the fused Shan-Chen extended-stencil step on one MI355X.
+
+Workload (one "step" = one time step of the whole lattice: pull-stream, moments, psi, the
+24-vector wide-stencil force, BGK + Guo collision): D2Q9, 4096 x 4096 periodic sites,
+forcing shells {1,2,4,5,8} with seeded free weights satisfying e2 = 1, I40 = I60 = 0,
+psi = exp(-1/n), G = 1.2 G_c (reduced temperature 0.2), tau = 1, spinodal start
+n ~ U(0.5, 1.5); populations stored in FP32 as shifted deviations g = f - w rho0.
+
+Prints one JSON line. MLUPS = sites x steps / time / 1e6. The roofline object prices the
+step kernel against HBM: algorithmic bytes per site-step are 2 Q s (each population read
+once and written once, s = bytes per stored value).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & %HBM roofline, FP32 vs FP64 at stated error; adjoint/forward cost ratio"
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "D2Q9 4096x4096 periodic, extended forcing stencil shells {1,2,4,5,8} (24 vectors, seeded weights), spinodal start U(0.5,1.5), 2000-step run"
+DIMS = (4096, 4096)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step2d_c2_traffic.json")
+KERNEL_SOURCES = ["paper_2505_23647_amd/csrc/step2d.hpp", "paper_2505_23647_amd/csrc/scl_common.hpp"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def workload_inputs():
+    from paper_2505_23647_amd import stencil, synth
+    u = synth.knob_draws(2, 2, 0.0, 1.0)
+    e4, e8, W = stencil.seeded_family2d(u[0], u[1])
+    G = -1.2 * np.e ** 2          # 1.2 x the critical coupling -e^2 of psi = exp(-1/n), e2 = 1
+    n0 = synth.uniform(DIMS, 0.5, 1.5, seed=1)
+    return e4, e8, W, G, n0
+
+
+def make_lattice(prec, W, G, n0, stream):
+    from paper_2505_23647_amd import Lattice
+    lat = Lattice([DIMS], prec, stream=stream)
+    lat.set_physics(1.0, G).set_stencil([1, 2, 4, 5, 8], W).init_density(n0)
+    return lat
+
+
+def timed(lat, steps, warmup):
+    lat.step(warmup)
+    ms = lat.step_timed(steps)
+    return ms
+
+
+def cpu_baseline(W, G, n0_full, budget_s=12.0):
+    """The FP64 oracle on the host cores, on a 1024 x 1024 crop of the same workload."""
+    import oracle
+    crop = n0_full.reshape(DIMS[1], DIMS[0])[:1024, :1024].copy()
+    s = oracle.Sim((1024, 1024), 1.0, G, [1, 2, 4, 5, 8], W).init_density(crop)
+    s.run(2)  # first touch
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < budget_s:
+        s.run(5)
+        steps += 5
+    dt = time.perf_counter() - t0
+    return {"value": round(1024 * 1024 * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle, 1024x1024 crop of the same initial field and stencil, {steps} steps in {dt:.1f} s"}
+
+
+def load_traffic(bytes_alg):
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    t = json.load(open(TRAFFIC_FILE))
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def copy_calibration():
+    """A plain device copy of known size (for scaling the FETCH_SIZE / WRITE_SIZE counters)."""
+    import torch
+    n = 1 << 28  # 1 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    if args.mode == "copy":
+        copy_calibration()
+        return
+
+    import torch
+    from paper_2505_23647_amd import SCL_FP16S_FP32, SCL_FP32_SHIFTED, SCL_FP64
+
+    torch.cuda.init()
+    stream = torch.cuda.current_stream().cuda_stream
+    e4, e8, W, G, n0 = workload_inputs()
+    cells = DIMS[0] * DIMS[1]
+
+    lat = make_lattice(SCL_FP32_SHIFTED, W, G, n0, stream)
+    if args.tune:
+        lat.tune()
+    torch.cuda.synchronize()
+    ms = timed(lat, args.steps, args.warmup)
+    torch.cuda.synchronize()
+    mlups = cells * args.steps / (ms / 1e3) / 1e6
+    bytes_alg = 2 * 9 * 4 * cells
+    avg_s = ms / 1e3 / args.steps
+    achieved = bytes_alg / avg_s / 1e9
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "sites": cells, "stencil_vectors": 24, "precision": "FP32 shifted",
+                   "e4": round(float(e4), 6), "e8": round(float(e8), 6), "G": G, "tau": 1.0,
+                   "tiling": list(lat.get_tiling())},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(bytes_alg),
+                     "bytes_alg_per_launch": bytes_alg, "kernel": "k_step2d (fused step)"},
+    }
+    if not args.no_variants:
+        var = {}
+        n_fp32 = lat.density()
+        for name, prec, s in (("fp64", SCL_FP64, 8), ("fp16_storage", SCL_FP16S_FP32, 2)):
+            lv = make_lattice(prec, W, G, n0, stream)
+            msv = timed(lv, args.steps, args.warmup)
+            ml = cells * args.steps / (msv / 1e3) / 1e6
+            ach = 2 * 9 * s * cells / (msv / 1e3 / args.steps) / 1e9
+            var[name] = {"MLUPS": round(ml, 1), "achieved_GBs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4)}
+            if prec == SCL_FP64:
+                n64 = lv.density()
+                var["fp32_shifted_vs_fp64_density_rel_err"] = float(np.abs(n_fp32 - n64).max() / np.abs(n64).max())
+            lv.close()
+        out["variants"] = var
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(W, G, n0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

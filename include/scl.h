@@ -1,0 +1,183 @@
+/*
+ * scl.h - C ABI of libscl, an MI355X (gfx950) implementation of the Shan-Chen multiphase
+ * lattice Boltzmann time step with an extended, tunable forcing stencil
+ * (Lulli & Ching, "Higher-order Tuning of Interface Physics in Multiphase Lattice
+ * Boltzmann", arXiv 2505.23647).
+ *
+ * One time step, per lattice site x (Sec. "Lattice Boltzmann" and Sec. "Shan-Chen Model"):
+ *   n = sum_i f_i, j = sum_i f_i xi_i, psi = psi(n)
+ *   F(x) = -G c_s^2 psi(x) sum_a W(|e_a|^2) psi(x + e_a) e_a                     eq. (sc_f)
+ *   u = (j + F/2) / n                                       (shifted velocity after eq. GuoForcing)
+ *   f_i(x + xi_i, t+1) = f_i - (f_i - f_i^eq(n, u))/tau + F_i(u, F)       eqs. (lbm), (omega_i),
+ *                                                                         (f_eq), (GuoForcing)
+ * with c_s^2 = 1/3, the second-order Hermite equilibrium, Guo forcing with T = 2 u F, and
+ * periodic boundaries in every direction.
+ *
+ * Conventions shared by every call
+ *   - Every call returns scl_status; nothing throws across the ABI. scl_last_error() gives a
+ *     thread-local text for the last failure on the calling thread.
+ *   - Arguments are validated before any device work; a rejected call changes nothing.
+ *   - The lattice owns its device buffers. The caller owns every array it passes (host or
+ *     device) and keeps it alive for the duration of the call only.
+ *   - Device work is ordered on the HIP stream given to scl_create (NULL = the default
+ *     stream). Calls that return host data synchronise that stream before returning.
+ *   - Site order: domains one after the other (in the order given to scl_create); inside a
+ *     domain x fastest, then y, then z. "cells" below is the total over all domains.
+ *   - Population layout: domain by domain, each domain a [Q][cells_of_domain] block.
+ *   - Velocity order (see scl_velocity_set): D2Q9 rest, (1,0), (0,1), (-1,0), (0,-1),
+ *     (1,1), (-1,1), (-1,-1), (1,-1); D3Q19 rest, +-x, +-y, +-z faces, then the 12 edges.
+ *   - Shell codes name forcing-vector symmetry groups: the code is |e|^2, all vectors that a
+ *     generator reaches by permutations and sign flips (Fig. 1 and Sec. on sigma_1 tuning).
+ *     Supported: 2D {1,2,4,5,8}; 3D {1,2,3,4,5,6,8}.
+ *   - G follows eq. (sc_f): the force carries an explicit c_s^2, and the critical coupling of
+ *     psi = exp(-1/n) with e_2 = 1 is G_c = -e^2.
+ */
+#ifndef SCL_H
+#define SCL_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SCL_ABI_VERSION 1
+
+typedef struct scl_lattice_s* scl_lattice;
+
+typedef enum {
+  SCL_OK = 0,
+  SCL_E_INVALID = 1,     /* bad argument (sizes, values, shell codes, missing pointer) */
+  SCL_E_NOMEM = 2,       /* device allocation failed */
+  SCL_E_DEVICE = 3,      /* a HIP call failed; scl_last_error() holds hipGetErrorString */
+  SCL_E_STATE = 4,       /* call out of order (e.g. scl_step before scl_init_density) */
+  SCL_E_NONFINITE = 5,   /* a checked readout found NaN or Inf (the run diverged) */
+  SCL_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+} scl_status;
+
+typedef enum { SCL_D2Q9 = 0, SCL_D3Q19 = 1 } scl_velset;
+
+/* Storage / arithmetic of the populations.
+ *   SCL_FP64          double storage, double arithmetic.
+ *   SCL_FP32          float storage, float arithmetic.
+ *   SCL_FP32_SHIFTED  float storage of g_i = f_i - w_i rho0 (rho0 = the domain's mean initial
+ *                     density), float arithmetic on the deviations.
+ *   SCL_FP16S_FP32    IEEE binary16 storage of g_i (round to nearest even), float arithmetic.
+ * Readouts (mass, momentum, pressure tensor, observables) are always accumulated in double. */
+typedef enum { SCL_FP64 = 0, SCL_FP32 = 1, SCL_FP32_SHIFTED = 2, SCL_FP16S_FP32 = 3 } scl_precision;
+
+/* Pseudopotential psi(n).
+ *   SCL_PSI_EXP      exp(-1/n)                      (eps = 0 case, Sec. on sigma_1 tuning)
+ *   SCL_PSI_EPS      (n / (eps + n))^(1/eps)        eq. (psieps); eps > 0 from psi_param
+ *   SCL_PSI_CLASSIC  1 - exp(-n)                    textbook form, not used by the paper */
+typedef enum { SCL_PSI_EXP = 0, SCL_PSI_EPS = 1, SCL_PSI_CLASSIC = 2 } scl_psi;
+
+/* ABI version of the loaded library (SCL_ABI_VERSION of the build). */
+int32_t scl_abi_version(void);
+
+/* Text of the last error on this thread ("" if none). Owned by the library. */
+const char* scl_last_error(void);
+
+/* Velocity set of vs: writes Q vectors (3 ints each, z = 0 in 2D) to xi and Q weights to w
+ * (either may be NULL); returns Q, or -1 for an unknown vs. */
+int32_t scl_velocity_set(scl_velset vs, int32_t* xi, double* w);
+
+/* Create a lattice of ndom independent periodic domains.
+ *   dims: ndom x 3 ints (nx, ny, nz), nz = 1 for D2Q9. Each extent must be >= 1; the
+ *         domain must hold at least one site. Batched domains may differ in size.
+ *   hip_stream: hipStream_t on which all work is ordered (NULL = default stream).
+ * Allocates two population buffers (A/B) of Q x cells x sizeof(storage). */
+scl_status scl_create(scl_velset vs, scl_precision prec, int32_t ndom, const int32_t* dims,
+                      void* hip_stream, scl_lattice* out);
+
+/* Free every device buffer of the lattice. NULL is accepted. */
+scl_status scl_destroy(scl_lattice lat);
+
+/* Physics per domain (arrays of ndom doubles): relaxation time tau > 1/2, coupling G
+ * (eq. sc_f convention; any finite value), pseudopotential kind and its parameter
+ * (eps > 0 for SCL_PSI_EPS; ignored otherwise; psi_param may be NULL then). */
+scl_status scl_set_physics(scl_lattice lat, const double* tau, const double* G, scl_psi kind,
+                           const double* psi_param);
+
+/* Forcing stencil (eq. sc_f): nshells distinct shell codes and the weights W(code) per
+ * domain, W laid out ndom x nshells. Weights must be finite. */
+scl_status scl_set_stencil(scl_lattice lat, int32_t nshells, const int32_t* shell_codes, const double* W);
+
+/* Initial state f_i(x, 0) = w_i n0(x): the fluid at rest. n0 holds cells doubles (host, or
+ * device when is_device_ptr != 0), every value finite and > 0. Resets the step counter and,
+ * for shifted storage, sets rho0 per domain to the mean of n0 over that domain. */
+scl_status scl_init_density(scl_lattice lat, const double* n0, int32_t is_device_ptr);
+
+/* Advance every domain by nsteps >= 0 time steps (asynchronous on the lattice stream).
+ * Needs scl_set_physics, scl_set_stencil and scl_init_density first (SCL_E_STATE). */
+scl_status scl_step(scl_lattice lat, int64_t nsteps);
+
+/* As scl_step, and returns the elapsed device time of the whole call in milliseconds,
+ * measured with HIP events recorded on the lattice stream around the launches. */
+scl_status scl_step_timed(scl_lattice lat, int64_t nsteps, double* ms);
+
+/* Number of steps taken since scl_init_density. */
+scl_status scl_get_step_count(scl_lattice lat, int64_t* steps);
+
+/* Density n = sum_i f_i of the current state, cells doubles (host or device). */
+scl_status scl_get_density(scl_lattice lat, double* out, int32_t is_device_ptr);
+
+/* Velocity u = (j + F/2)/n of the current state, laid out d x cells (all x, then all y...). */
+scl_status scl_get_velocity(scl_lattice lat, double* out, int32_t is_device_ptr);
+
+/* Force F (eq. sc_f) of the current state, laid out d x cells. */
+scl_status scl_get_force(scl_lattice lat, double* out, int32_t is_device_ptr);
+
+/* Populations f_i(x, t) of the current state (the post-streaming values), in the population
+ * layout above, as doubles. */
+scl_status scl_get_populations(scl_lattice lat, double* out, int32_t is_device_ptr);
+
+/* Replace the state by the given populations (same layout as scl_get_populations), rounded
+ * to the storage precision. Keeps the step counter and rho0. */
+scl_status scl_set_populations(scl_lattice lat, const double* in, int32_t is_device_ptr);
+
+/* Per-domain mass M = sum_x n and total physical momentum sum_x (j + F/2), accumulated in
+ * double with a fixed-order tree (bitwise reproducible). mass: ndom doubles; momentum:
+ * ndom x d doubles (may be NULL). Returns SCL_E_NONFINITE if any mass is NaN or Inf. */
+scl_status scl_reduce_conserved(scl_lattice lat, double* mass, double* momentum);
+
+/* Lattice pressure tensor of the current state in double (D2Q9 only): out holds 3 x cells
+ * values, the planes Pxx, Pyy, Pxy. Follows the d = 2 appendix on the lattice pressure
+ * tensor (groups along a line plus the irregular pairs of |e|^2 = 5) with the ideal part
+ * n c_s^2 delta added (Sec. "Interface Physics"). D3Q19 returns SCL_E_UNSUPPORTED. */
+scl_status scl_get_pressure_tensor(scl_lattice lat, double* out, int32_t is_device_ptr);
+
+/* Droplet / bubble observables of each square D2Q9 domain (Sec. "Interface Physics" and the
+ * Laplace-law paragraph of the sigma_1 tuning section), in double:
+ *   Pbar = (Pxx + Pyy)/2, dP = Pbar(centre) - Pbar(corner (0,0));
+ *   C_d = int_0^{L/2} r (Pbar(corner) - Pyy(centre + r e_x)) dr, trapezoid on sites, mean of
+ *         the +x and -x half-lines;
+ *   R_s = sqrt(2 C_d / dP), sigma_s = (-1)^b dP R_s (stationary point of sigma[R]);
+ *   R_e from pi R_e^2 n(centre) + (L^2 - pi R_e^2) n(corner) = M.
+ * center: ndom x 2 ints (x, y); is_bubble: ndom bytes (b), may be NULL (droplets).
+ * out: ndom x 6 doubles (dP, C_d, R_s, sigma_s, R_e, R_e - R_s). Host arrays. */
+scl_status scl_droplet_observables(scl_lattice lat, const int32_t* center, const int8_t* is_bubble,
+                                   double* out);
+
+/* Tiling of the fused step: strip = lanes per workgroup along x (64, 128 or 256 in 2D;
+ * 3D: 0 = default tile), seg = rows (2D) or planes (3D) marched by one workgroup (>= 1).
+ * 0 keeps the current value. */
+scl_status scl_set_tiling(scl_lattice lat, int32_t strip, int32_t seg);
+scl_status scl_get_tiling(scl_lattice lat, int32_t* strip, int32_t* seg);
+
+/* Autotuner: times the candidate tilings on this lattice (advancing it by the steps it
+ * uses, see scl_get_step_count) and keeps the fastest. If cache_path is not NULL the choice
+ * is read from / appended to that text file, keyed by device name, velocity set, stencil
+ * reach, precision and domain sizes. */
+scl_status scl_tune(scl_lattice lat, const char* cache_path);
+
+/* Replay the step loop through HIP graphs of k launches (k even, 0 = plain launches).
+ * The graph is captured on first use and re-captured after any change of tiling,
+ * physics, stencil or state. */
+scl_status scl_set_graph_steps(scl_lattice lat, int32_t k);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCL_H */

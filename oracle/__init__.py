@@ -171,3 +171,8 @@ def droplet_tangent_linear(dims, tau, G, codes, W, n0, nsteps, center, bubble=Fa
     if rc != 0:
         raise RuntimeError(f"oracle tangent-linear run failed ({rc})")
     return obs, jac
+
+
+def num_threads() -> int:
+    """Threads used by the oracle's OpenMP loops."""
+    return int(lib().orc_num_threads())

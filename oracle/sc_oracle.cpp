@@ -30,6 +30,9 @@
 #include <vector>
 #include <array>
 #include <algorithm>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace orc {
 
@@ -366,6 +369,15 @@ static void droplet_obs2d(const Geom& g, const Stencil& st, const int* codes, co
 using namespace orc;
 
 extern "C" {
+
+// Threads the OpenMP loops use.
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 // Velocity set: writes Q vectors (3 ints each) and weights; returns Q.
 int orc_velset(int d, int* xi, double* w) {

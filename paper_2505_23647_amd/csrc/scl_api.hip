@@ -1,0 +1,892 @@
+// libscl host side: the C ABI of include/scl.h, kernel dispatch, tiling, graphs, autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "scl.h"
+#include "scl_common.hpp"
+#include "step2d.hpp"
+#include "step3d.hpp"
+#include "readout.hpp"
+#include "adjoint.hpp"
+
+using namespace scl;
+
+namespace {
+
+thread_local std::string g_err;
+
+scl_status fail(scl_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(SCL_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t storage_bytes(scl_precision p) {
+  switch (p) {
+    case SCL_FP64: return 8;
+    case SCL_FP32: case SCL_FP32_SHIFTED: return 4;
+    case SCL_FP16S_FP32: return 2;
+  }
+  return 0;
+}
+
+// Shell codes of the compile-time sets (index = weight slot).
+const int SET2[2][5] = {{1, 2, 0, 0, 0}, {1, 2, 4, 5, 8}};
+const int SET2N[2] = {2, 5};
+const int SET3[2][7] = {{1, 2, 3, 0, 0, 0, 0}, {1, 2, 3, 4, 5, 6, 8}};
+const int SET3N[2] = {3, 7};
+
+// 3D tile shapes selectable through scl_set_tiling(strip = index).
+struct Tile3 { int tx, ty; };
+const Tile3 TILES3[4] = {{0, 0}, {32, 8}, {32, 16}, {32, 32}};
+
+}  // namespace
+
+struct scl_lattice_s {
+  scl_velset vs;
+  scl_precision prec;
+  int d, Q;
+  int ndom;
+  std::vector<int> nx, ny, nz;
+  std::vector<long long> off;
+  long long cells = 0;
+  hipStream_t stream = nullptr;    // caller's stream (may be the null stream)
+  hipStream_t launch = nullptr;    // stream the step kernels go to (the capture stream while capturing)
+  hipStream_t cap = nullptr;       // private stream used only to capture graphs
+  void* A = nullptr;  // current state (post-collision values, pull layout)
+  void* B = nullptr;  // scratch for the next state
+  // physics
+  bool have_physics = false, have_stencil = false, have_state = false;
+  std::vector<double> tau, G, psi_param, rho0;
+  int psi_kind = 0;
+  int set = 1;                     // compile-time shell set
+  std::vector<int> user_codes;     // as given
+  std::vector<int> slot_of_user;   // user shell -> set slot
+  std::vector<double> Wslot;       // ndom x MAX_SHELLS
+  // device tables
+  DomDev* d_doms = nullptr;
+  WorkItem* d_items = nullptr;
+  int nitems = 0;
+  bool dirty_doms = true, dirty_items = true;
+  // tiling
+  int strip = 256, seg = 0;        // 2D: lanes per workgroup, rows per item (0 = auto)
+  int tile3 = 2, seg3 = 0;         // 3D: tile index, planes per item (0 = auto)
+  // graphs
+  int graph_k = 0;
+  hipGraphExec_t gexec = nullptr;
+  void* gexec_A = nullptr;         // buffer that was "A" when the graph was captured
+  // readout scratch (double)
+  double *d_n = nullptr, *d_psi = nullptr, *d_j = nullptr, *d_F = nullptr, *d_tmp = nullptr;
+  double* d_part = nullptr;
+  size_t part_cap = 0;
+  int64_t steps = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // adjoint state
+  AdjointState adj;
+};
+
+namespace {
+
+std::vector<DomDev> host_doms(const scl_lattice_s* L) {
+  std::vector<DomDev> v(L->ndom);
+  for (int k = 0; k < L->ndom; ++k) {
+    DomDev& d = v[k];
+    std::memset(&d, 0, sizeof(d));
+    d.off = L->off[k];
+    d.nx = L->nx[k]; d.ny = L->ny[k]; d.nz = L->nz[k];
+    d.psi_kind = L->psi_kind;
+    d.omega = 1.0 / L->tau[k];
+    d.kappa = 1.0 - 0.5 / L->tau[k];
+    d.gpre = -L->G[k] * CS2;
+    d.eps = L->psi_param[k];
+    d.inv_eps = L->psi_param[k] != 0.0 ? 1.0 / L->psi_param[k] : 0.0;
+    d.rho0 = L->rho0[k];
+    for (int s = 0; s < MAX_SHELLS; ++s) d.W[s] = L->Wslot[(size_t)k * MAX_SHELLS + s];
+  }
+  return v;
+}
+
+int stencil_reach(const scl_lattice_s* L) { return L->set == 0 ? 1 : 2; }
+
+// All forcing vectors (both of every pair) of the lattice's compile-time set.
+VecTable full_table(const scl_lattice_s* L) {
+  VecTable t{};
+  t.n = 0;
+  if (L->d == 2) {
+    auto add = [&](auto sh_tag) {
+      using SH = decltype(sh_tag);
+      for (int k = 0; k < SH::NH; ++k) {
+        HalfVec h = SH::h(k);
+        t.v[t.n++] = h;
+        t.v[t.n++] = HalfVec{(int8_t)-h.x, (int8_t)-h.y, (int8_t)-h.z, h.slot};
+      }
+    };
+    if (L->set == 0) add(Shells<2, 0>{}); else add(Shells<2, 1>{});
+  } else {
+    Half3Table h = make_half3(L->set);
+    for (int k = 0; k < h.n; ++k) {
+      t.v[t.n++] = h.v[k];
+      t.v[t.n++] = HalfVec{(int8_t)-h.v[k].x, (int8_t)-h.v[k].y, (int8_t)-h.v[k].z, h.v[k].slot};
+    }
+  }
+  return t;
+}
+
+scl_status build_items(scl_lattice_s* L) {
+  std::vector<WorkItem> items;
+  const int R = stencil_reach(L);
+  if (L->d == 2) {
+    const int outw = L->strip - 2 * R;
+    long long ncols_items = 0, rows = 0;
+    for (int k = 0; k < L->ndom; ++k) {
+      ncols_items += (L->nx[k] + outw - 1) / outw;
+      rows = std::max<long long>(rows, L->ny[k]);
+    }
+    int seg = L->seg;
+    if (seg <= 0) {
+      // aim for about 2048 workgroups (8 per CU) but at least 32 rows per item
+      long long work = 0;
+      for (int k = 0; k < L->ndom; ++k) work += (long long)((L->nx[k] + outw - 1) / outw) * L->ny[k];
+      seg = (int)std::max<long long>(32, (work + 2047) / 2048);
+    }
+    for (int k = 0; k < L->ndom; ++k) {
+      const int ns = (L->nx[k] + outw - 1) / outw;
+      for (int y0 = 0; y0 < L->ny[k]; y0 += seg)
+        for (int s = 0; s < ns; ++s) {
+          WorkItem w{};
+          w.dom = k; w.x0 = s * outw; w.y0 = y0; w.y1 = std::min(y0 + seg, L->ny[k]);
+          w.z0 = 0; w.z1 = 1;
+          items.push_back(w);
+        }
+    }
+    (void)ncols_items; (void)rows;
+  } else {
+    const Tile3 t = TILES3[L->tile3];
+    const int ox = t.tx - 2 * R, oy = t.ty - 2 * R;
+    int seg = L->seg3;
+    if (seg <= 0) {
+      long long work = 0;
+      for (int k = 0; k < L->ndom; ++k)
+        work += (long long)((L->nx[k] + ox - 1) / ox) * ((L->ny[k] + oy - 1) / oy) * L->nz[k];
+      seg = (int)std::max<long long>(16, (work + 2047) / 2048);
+    }
+    for (int k = 0; k < L->ndom; ++k)
+      for (int z0 = 0; z0 < L->nz[k]; z0 += seg)
+        for (int y0 = 0; y0 < L->ny[k]; y0 += oy)
+          for (int x0 = 0; x0 < L->nx[k]; x0 += ox) {
+            WorkItem w{};
+            w.dom = k; w.x0 = x0; w.y0 = y0; w.y1 = std::min(y0 + oy, L->ny[k]);
+            w.z0 = z0; w.z1 = std::min(z0 + seg, L->nz[k]);
+            items.push_back(w);
+          }
+  }
+  if (L->d_items) { HIPCHK(hipFree(L->d_items)); L->d_items = nullptr; }
+  HIPCHK(hipMalloc(&L->d_items, sizeof(WorkItem) * items.size()));
+  HIPCHK(hipMemcpy(L->d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice));
+  L->nitems = (int)items.size();
+  L->dirty_items = false;
+  return SCL_OK;
+}
+
+scl_status sync_params(scl_lattice_s* L) {
+  if (L->dirty_doms) {
+    std::vector<DomDev> v = host_doms(L);
+    if (!L->d_doms) HIPCHK(hipMalloc(&L->d_doms, sizeof(DomDev) * L->ndom));
+    HIPCHK(hipMemcpyAsync(L->d_doms, v.data(), sizeof(DomDev) * L->ndom, hipMemcpyHostToDevice, L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));
+    L->dirty_doms = false;
+  }
+  if (L->dirty_items) {
+    scl_status s = build_items(L);
+    if (s != SCL_OK) return s;
+  }
+  return SCL_OK;
+}
+
+void drop_graph(scl_lattice_s* L) {
+  if (L->gexec) { (void)hipGraphExecDestroy(L->gexec); L->gexec = nullptr; }
+}
+
+// ------------------------------------------------------------------ step dispatch
+template <class S, class M, bool SHIFT>
+hipError_t launch2d(scl_lattice_s* L, const void* fin, void* fout, MacroRec<M> rec, bool record) {
+  const dim3 grid(L->nitems);
+  auto go = [&](auto kern, int nt) {
+    hipLaunchKernelGGL(kern, grid, dim3(nt), 0, L->launch, (const S*)fin, (S*)fout, L->d_doms, L->d_items, rec);
+  };
+#define SCL_2D_CASE(SETV, NTV)                                                     \
+  if (L->set == SETV && L->strip == NTV) {                                          \
+    if (record) go(k_step2d<S, M, SETV, NTV, SHIFT, true>, NTV);                    \
+    else go(k_step2d<S, M, SETV, NTV, SHIFT, false>, NTV);                          \
+    return hipGetLastError();                                                       \
+  }
+  SCL_2D_CASE(0, 64) SCL_2D_CASE(0, 128) SCL_2D_CASE(0, 256)
+  SCL_2D_CASE(1, 64) SCL_2D_CASE(1, 128) SCL_2D_CASE(1, 256)
+#undef SCL_2D_CASE
+  return hipErrorInvalidValue;
+}
+
+template <class S, class M, bool SHIFT>
+hipError_t launch3d(scl_lattice_s* L, const void* fin, void* fout) {
+  const dim3 grid(L->nitems);
+#define SCL_3D_CASE(SETV, TI, TXV, TYV)                                                          \
+  if (L->set == SETV && L->tile3 == TI) {                                                          \
+    hipLaunchKernelGGL((k_step3d<S, M, SETV, TXV, TYV, SHIFT>), grid, dim3(TXV * TYV), 0, L->launch, \
+                       (const S*)fin, (S*)fout, L->d_doms, L->d_items);                           \
+    return hipGetLastError();                                                                     \
+  }
+  SCL_3D_CASE(0, 1, 32, 8) SCL_3D_CASE(0, 2, 32, 16) SCL_3D_CASE(1, 1, 32, 8) SCL_3D_CASE(1, 2, 32, 16)
+  if (sizeof(M) == 4) {
+    SCL_3D_CASE(0, 3, 32, 32) SCL_3D_CASE(1, 3, 32, 32)
+  }
+#undef SCL_3D_CASE
+  return hipErrorInvalidValue;
+}
+
+// One step from A into B (no swap).
+hipError_t launch_step(scl_lattice_s* L, const void* fin, void* fout, const MacroRec<double>* rec64,
+                       const MacroRec<float>* rec32) {
+  if (L->d == 2) {
+    switch (L->prec) {
+      case SCL_FP64:
+        return launch2d<double, double, false>(L, fin, fout, rec64 ? *rec64 : MacroRec<double>{}, rec64 != nullptr);
+      case SCL_FP32:
+        return launch2d<float, float, false>(L, fin, fout, rec32 ? *rec32 : MacroRec<float>{}, rec32 != nullptr);
+      case SCL_FP32_SHIFTED:
+        return launch2d<float, float, true>(L, fin, fout, rec32 ? *rec32 : MacroRec<float>{}, rec32 != nullptr);
+      case SCL_FP16S_FP32:
+        return launch2d<_Float16, float, true>(L, fin, fout, MacroRec<float>{}, false);
+    }
+  } else {
+    switch (L->prec) {
+      case SCL_FP64: return launch3d<double, double, false>(L, fin, fout);
+      case SCL_FP32: return launch3d<float, float, false>(L, fin, fout);
+      case SCL_FP32_SHIFTED: return launch3d<float, float, true>(L, fin, fout);
+      case SCL_FP16S_FP32: return launch3d<_Float16, float, true>(L, fin, fout);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+scl_status ready(scl_lattice_s* L) {
+  if (!L->have_physics) return fail(SCL_E_STATE, "scl_set_physics has not been called");
+  if (!L->have_stencil) return fail(SCL_E_STATE, "scl_set_stencil has not been called");
+  if (!L->have_state) return fail(SCL_E_STATE, "scl_init_density has not been called");
+  return sync_params(L);
+}
+
+scl_status plain_steps(scl_lattice_s* L, int64_t n) {
+  for (int64_t s = 0; s < n; ++s) {
+    hipError_t e = launch_step(L, L->A, L->B, nullptr, nullptr);
+    if (e != hipSuccess) return fail(SCL_E_DEVICE, std::string("step launch: ") + hipGetErrorString(e));
+    std::swap(L->A, L->B);
+    L->steps++;
+  }
+  return SCL_OK;
+}
+
+scl_status do_steps(scl_lattice_s* L, int64_t n) {
+  scl_status s = ready(L);
+  if (s != SCL_OK) return s;
+  if (L->graph_k <= 0 || n < L->graph_k) return plain_steps(L, n);
+  const int k = L->graph_k;
+  // the graph alternates A/B k times (k even), so it is valid whenever A is the buffer it
+  // was captured with.
+  if (L->gexec && L->gexec_A != L->A) drop_graph(L);
+  if (!L->gexec) {
+    // capture on a private stream (the caller's may be the null stream, which cannot be
+    // captured); the instantiated graph is then launched on the caller's stream.
+    if (!L->cap) HIPCHK(hipStreamCreateWithFlags(&L->cap, hipStreamNonBlocking));
+    hipGraph_t g;
+    HIPCHK(hipStreamBeginCapture(L->cap, hipStreamCaptureModeThreadLocal));
+    L->launch = L->cap;
+    void* a = L->A;
+    void* b = L->B;
+    for (int q = 0; q < k; ++q) {
+      hipError_t e = launch_step(L, a, b, nullptr, nullptr);
+      if (e != hipSuccess) {
+        hipGraph_t dummy;
+        (void)hipStreamEndCapture(L->cap, &dummy);
+        L->launch = L->stream;
+        return fail(SCL_E_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+      }
+      std::swap(a, b);
+    }
+    L->launch = L->stream;
+    HIPCHK(hipStreamEndCapture(L->cap, &g));
+    HIPCHK(hipGraphInstantiate(&L->gexec, g, nullptr, nullptr, 0));
+    HIPCHK(hipGraphDestroy(g));
+    L->gexec_A = L->A;
+  }
+  int64_t done = 0;
+  while (n - done >= k) {
+    HIPCHK(hipGraphLaunch(L->gexec, L->stream));
+    done += k;
+    L->steps += k;
+  }
+  return plain_steps(L, n - done);
+}
+
+scl_status ensure_scratch(scl_lattice_s* L) {
+  if (!L->d_n) {
+    const size_t c = (size_t)L->cells;
+    HIPCHK(hipMalloc(&L->d_n, c * sizeof(double)));
+    HIPCHK(hipMalloc(&L->d_psi, c * sizeof(double)));
+    HIPCHK(hipMalloc(&L->d_j, 3 * c * sizeof(double)));
+    HIPCHK(hipMalloc(&L->d_F, 3 * c * sizeof(double)));
+    HIPCHK(hipMalloc(&L->d_tmp, 3 * c * sizeof(double)));
+  }
+  return SCL_OK;
+}
+
+inline unsigned blocks_for(long long n, int nt) { return (unsigned)((n + nt - 1) / nt); }
+
+// n, psi, j, F of the current state into the double scratch arrays.
+scl_status compute_fields(scl_lattice_s* L, bool with_force) {
+  scl_status s = ready(L);
+  if (s != SCL_OK) return s;
+  s = ensure_scratch(L);
+  if (s != SCL_OK) return s;
+  std::vector<DomDev> doms = host_doms(L);
+  VecTable tab = full_table(L);
+  for (int k = 0; k < L->ndom; ++k) {
+    const long long c = (long long)L->nx[k] * L->ny[k] * L->nz[k];
+    const unsigned nb = blocks_for(c, 256);
+#define FIELDS(VS, S) hipLaunchKernelGGL((k_fields<VS, S>), dim3(nb), dim3(256), 0, L->stream, (const S*)L->A, L->d_n, L->d_psi, L->d_j, L->cells, doms[k])
+    if (L->vs == SCL_D2Q9) {
+      if (L->prec == SCL_FP64) FIELDS(0, double);
+      else if (L->prec == SCL_FP16S_FP32) FIELDS(0, _Float16);
+      else FIELDS(0, float);
+    } else {
+      if (L->prec == SCL_FP64) FIELDS(1, double);
+      else if (L->prec == SCL_FP16S_FP32) FIELDS(1, _Float16);
+      else FIELDS(1, float);
+    }
+#undef FIELDS
+    HIPCHK(hipGetLastError());
+  }
+  if (with_force) {
+    for (int k = 0; k < L->ndom; ++k) {
+      const long long c = (long long)L->nx[k] * L->ny[k] * L->nz[k];
+      if (L->d == 2) hipLaunchKernelGGL(k_force<2>, dim3(blocks_for(c, 256)), dim3(256), 0, L->stream, L->d_psi, L->d_F, L->cells, doms[k], tab);
+      else hipLaunchKernelGGL(k_force<3>, dim3(blocks_for(c, 256)), dim3(256), 0, L->stream, L->d_psi, L->d_F, L->cells, doms[k], tab);
+      HIPCHK(hipGetLastError());
+    }
+  }
+  return SCL_OK;
+}
+
+scl_status copy_out(scl_lattice_s* L, double* out, const double* src, size_t count, int is_dev) {
+  HIPCHK(hipMemcpyAsync(out, src, count * sizeof(double), is_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                        L->stream));
+  HIPCHK(hipStreamSynchronize(L->stream));
+  return SCL_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+int32_t scl_abi_version(void) { return SCL_ABI_VERSION; }
+
+const char* scl_last_error(void) { return g_err.c_str(); }
+
+int32_t scl_velocity_set(scl_velset vs, int32_t* xi, double* w) {
+  if (vs == SCL_D2Q9) {
+    for (int i = 0; i < 9; ++i) {
+      if (xi) { xi[3 * i] = Vel<0>::cx(i); xi[3 * i + 1] = Vel<0>::cy(i); xi[3 * i + 2] = 0; }
+      if (w) w[i] = Vel<0>::w(i);
+    }
+    return 9;
+  }
+  if (vs == SCL_D3Q19) {
+    for (int i = 0; i < 19; ++i) {
+      if (xi) { xi[3 * i] = Vel<1>::cx(i); xi[3 * i + 1] = Vel<1>::cy(i); xi[3 * i + 2] = Vel<1>::cz(i); }
+      if (w) w[i] = Vel<1>::w(i);
+    }
+    return 19;
+  }
+  return -1;
+}
+
+scl_status scl_create(scl_velset vs, scl_precision prec, int32_t ndom, const int32_t* dims, void* hip_stream,
+                      scl_lattice* out) {
+  if (!out) return fail(SCL_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (vs != SCL_D2Q9 && vs != SCL_D3Q19) return fail(SCL_E_INVALID, "unknown velocity set");
+  if (storage_bytes(prec) == 0) return fail(SCL_E_INVALID, "unknown precision");
+  if (ndom < 1 || !dims) return fail(SCL_E_INVALID, "need ndom >= 1 and dims");
+  std::unique_ptr<scl_lattice_s> L(new scl_lattice_s());
+  L->vs = vs;
+  L->prec = prec;
+  L->d = vs == SCL_D2Q9 ? 2 : 3;
+  L->Q = vs == SCL_D2Q9 ? 9 : 19;
+  L->ndom = ndom;
+  long long tot = 0;
+  for (int k = 0; k < ndom; ++k) {
+    const int x = dims[3 * k], y = dims[3 * k + 1], z = dims[3 * k + 2];
+    if (x < 1 || y < 1 || z < 1) return fail(SCL_E_INVALID, "every extent must be >= 1");
+    if (L->d == 2 && z != 1) return fail(SCL_E_INVALID, "D2Q9 domains need nz = 1");
+    L->nx.push_back(x); L->ny.push_back(y); L->nz.push_back(z);
+    L->off.push_back(tot);
+    tot += (long long)x * y * z;
+  }
+  L->cells = tot;
+  L->stream = (hipStream_t)hip_stream;
+  L->launch = L->stream;
+  L->tau.assign(ndom, 1.0);
+  L->G.assign(ndom, 0.0);
+  L->psi_param.assign(ndom, 0.0);
+  L->rho0.assign(ndom, 0.0);
+  L->Wslot.assign((size_t)ndom * MAX_SHELLS, 0.0);
+  const size_t bytes = (size_t)L->Q * tot * storage_bytes(prec);
+  if (hipMalloc(&L->A, bytes) != hipSuccess || hipMalloc(&L->B, bytes) != hipSuccess) {
+    if (L->A) (void)hipFree(L->A);
+    (void)hipGetLastError();
+    return fail(SCL_E_NOMEM, "population buffers do not fit in device memory");
+  }
+  HIPCHK(hipEventCreate(&L->ev0));
+  HIPCHK(hipEventCreate(&L->ev1));
+  *out = L.release();
+  return SCL_OK;
+}
+
+scl_status scl_destroy(scl_lattice L) {
+  if (!L) return SCL_OK;
+  drop_graph(L);
+  adjoint_free(L->adj);
+  void* ptrs[] = {L->A, L->B, L->d_doms, L->d_items, L->d_n, L->d_psi, L->d_j, L->d_F, L->d_tmp, L->d_part};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (L->cap) (void)hipStreamDestroy(L->cap);
+  if (L->ev0) (void)hipEventDestroy(L->ev0);
+  if (L->ev1) (void)hipEventDestroy(L->ev1);
+  delete L;
+  return SCL_OK;
+}
+
+scl_status scl_set_physics(scl_lattice L, const double* tau, const double* G, scl_psi kind, const double* psi_param) {
+  if (!L || !tau || !G) return fail(SCL_E_INVALID, "lattice, tau and G are required");
+  if (kind != SCL_PSI_EXP && kind != SCL_PSI_EPS && kind != SCL_PSI_CLASSIC)
+    return fail(SCL_E_INVALID, "unknown pseudopotential");
+  if (kind == SCL_PSI_EPS && !psi_param) return fail(SCL_E_INVALID, "SCL_PSI_EPS needs psi_param");
+  for (int k = 0; k < L->ndom; ++k) {
+    if (!(tau[k] > 0.5) || !std::isfinite(tau[k])) return fail(SCL_E_INVALID, "tau must be finite and > 1/2");
+    if (!std::isfinite(G[k])) return fail(SCL_E_INVALID, "G must be finite");
+    if (kind == SCL_PSI_EPS && !(psi_param[k] > 0.0 && std::isfinite(psi_param[k])))
+      return fail(SCL_E_INVALID, "eps must be finite and > 0");
+  }
+  for (int k = 0; k < L->ndom; ++k) {
+    L->tau[k] = tau[k];
+    L->G[k] = G[k];
+    L->psi_param[k] = (kind == SCL_PSI_EPS) ? psi_param[k] : 0.0;
+  }
+  L->psi_kind = (int)kind;
+  L->have_physics = true;
+  L->dirty_doms = true;
+  drop_graph(L);
+  return SCL_OK;
+}
+
+scl_status scl_set_stencil(scl_lattice L, int32_t nshells, const int32_t* codes, const double* W) {
+  if (!L || !codes || !W || nshells < 1 || nshells > MAX_SHELLS) return fail(SCL_E_INVALID, "bad stencil arguments");
+  const int* sets = L->d == 2 ? &SET2[0][0] : &SET3[0][0];
+  const int width = L->d == 2 ? 5 : 7;
+  const int* setn = L->d == 2 ? SET2N : SET3N;
+  int set = 0;
+  std::vector<int> slot(nshells, -1);
+  for (int s = 0; s < nshells; ++s) {
+    for (int q = 0; q < s; ++q)
+      if (codes[q] == codes[s]) return fail(SCL_E_INVALID, "repeated shell code");
+    bool in0 = false, in1 = false;
+    for (int q = 0; q < setn[0]; ++q) in0 |= sets[q] == codes[s];
+    for (int q = 0; q < setn[1]; ++q) in1 |= sets[width + q] == codes[s];
+    if (!in1) return fail(SCL_E_INVALID, "unsupported shell code " + std::to_string(codes[s]) +
+                                              (L->d == 2 ? " (2D supports 1,2,4,5,8)" : " (3D supports 1,2,3,4,5,6,8)"));
+    if (!in0) set = 1;
+  }
+  for (int k = 0; k < L->ndom; ++k)
+    for (int s = 0; s < nshells; ++s)
+      if (!std::isfinite(W[(size_t)k * nshells + s])) return fail(SCL_E_INVALID, "weights must be finite");
+  for (int s = 0; s < nshells; ++s)
+    for (int q = 0; q < setn[set]; ++q)
+      if (sets[set * width + q] == codes[s]) slot[s] = q;
+  L->set = set;
+  L->user_codes.assign(codes, codes + nshells);
+  L->slot_of_user = slot;
+  std::fill(L->Wslot.begin(), L->Wslot.end(), 0.0);
+  for (int k = 0; k < L->ndom; ++k)
+    for (int s = 0; s < nshells; ++s) L->Wslot[(size_t)k * MAX_SHELLS + slot[s]] = W[(size_t)k * nshells + s];
+  L->have_stencil = true;
+  L->dirty_doms = true;
+  L->dirty_items = true;
+  drop_graph(L);
+  return SCL_OK;
+}
+
+scl_status scl_init_density(scl_lattice L, const double* n0, int32_t is_dev) {
+  if (!L || !n0) return fail(SCL_E_INVALID, "lattice and n0 are required");
+  std::vector<double> h((size_t)L->cells);
+  if (is_dev) {
+    HIPCHK(hipMemcpyAsync(h.data(), n0, h.size() * sizeof(double), hipMemcpyDeviceToHost, L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));
+  } else {
+    std::memcpy(h.data(), n0, h.size() * sizeof(double));
+  }
+  for (size_t c = 0; c < h.size(); ++c)
+    if (!(h[c] > 0.0) || !std::isfinite(h[c])) return fail(SCL_E_INVALID, "initial density must be finite and > 0");
+  const bool shifted = L->prec == SCL_FP32_SHIFTED || L->prec == SCL_FP16S_FP32;
+  for (int k = 0; k < L->ndom; ++k) {
+    const long long c = (long long)L->nx[k] * L->ny[k] * L->nz[k];
+    double s = 0;
+    for (long long q = 0; q < c; ++q) s += h[(size_t)(L->off[k] + q)];
+    L->rho0[k] = shifted ? s / (double)c : 0.0;
+  }
+  L->dirty_doms = true;
+  double* dn = nullptr;
+  HIPCHK(hipMalloc(&dn, h.size() * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(dn, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, L->stream));
+  std::vector<DomDev> doms = host_doms(L);
+  for (int k = 0; k < L->ndom; ++k) {
+    const long long c = (long long)L->nx[k] * L->ny[k] * L->nz[k];
+    const unsigned nb = blocks_for(c, 256);
+#define INIT(VS, S) hipLaunchKernelGGL((k_init<VS, S>), dim3(nb), dim3(256), 0, L->stream, (S*)L->A, dn, doms[k])
+    if (L->vs == SCL_D2Q9) {
+      if (L->prec == SCL_FP64) INIT(0, double); else if (L->prec == SCL_FP16S_FP32) INIT(0, _Float16); else INIT(0, float);
+    } else {
+      if (L->prec == SCL_FP64) INIT(1, double); else if (L->prec == SCL_FP16S_FP32) INIT(1, _Float16); else INIT(1, float);
+    }
+#undef INIT
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipStreamSynchronize(L->stream));
+  HIPCHK(hipFree(dn));
+  L->have_state = true;
+  L->steps = 0;
+  drop_graph(L);
+  return SCL_OK;
+}
+
+scl_status scl_step(scl_lattice L, int64_t nsteps) {
+  if (!L || nsteps < 0) return fail(SCL_E_INVALID, "bad step arguments");
+  return do_steps(L, nsteps);
+}
+
+scl_status scl_step_timed(scl_lattice L, int64_t nsteps, double* ms) {
+  if (!L || nsteps < 0 || !ms) return fail(SCL_E_INVALID, "bad step arguments");
+  scl_status s = ready(L);
+  if (s != SCL_OK) return s;
+  HIPCHK(hipEventRecord(L->ev0, L->stream));
+  s = do_steps(L, nsteps);
+  if (s != SCL_OK) return s;
+  HIPCHK(hipEventRecord(L->ev1, L->stream));
+  HIPCHK(hipEventSynchronize(L->ev1));
+  float f = 0;
+  HIPCHK(hipEventElapsedTime(&f, L->ev0, L->ev1));
+  *ms = f;
+  return SCL_OK;
+}
+
+scl_status scl_get_step_count(scl_lattice L, int64_t* steps) {
+  if (!L || !steps) return fail(SCL_E_INVALID, "bad arguments");
+  *steps = L->steps;
+  return SCL_OK;
+}
+
+scl_status scl_get_density(scl_lattice L, double* out, int32_t is_dev) {
+  if (!L || !out) return fail(SCL_E_INVALID, "bad arguments");
+  scl_status s = compute_fields(L, false);
+  if (s != SCL_OK) return s;
+  return copy_out(L, out, L->d_n, (size_t)L->cells, is_dev);
+}
+
+scl_status scl_get_force(scl_lattice L, double* out, int32_t is_dev) {
+  if (!L || !out) return fail(SCL_E_INVALID, "bad arguments");
+  scl_status s = compute_fields(L, true);
+  if (s != SCL_OK) return s;
+  for (int q = 0; q < L->d; ++q) {
+    s = copy_out(L, out + (size_t)q * L->cells, L->d_F + (size_t)q * L->cells, (size_t)L->cells, is_dev);
+    if (s != SCL_OK) return s;
+  }
+  return SCL_OK;
+}
+
+scl_status scl_get_velocity(scl_lattice L, double* out, int32_t is_dev) {
+  if (!L || !out) return fail(SCL_E_INVALID, "bad arguments");
+  scl_status s = compute_fields(L, true);
+  if (s != SCL_OK) return s;
+  if (L->d == 2) hipLaunchKernelGGL(k_velocity<2>, dim3(blocks_for(L->cells, 256)), dim3(256), 0, L->stream, L->d_n, L->d_j, L->d_F, L->d_tmp, L->cells);
+  else hipLaunchKernelGGL(k_velocity<3>, dim3(blocks_for(L->cells, 256)), dim3(256), 0, L->stream, L->d_n, L->d_j, L->d_F, L->d_tmp, L->cells);
+  HIPCHK(hipGetLastError());
+  return copy_out(L, out, L->d_tmp, (size_t)L->d * L->cells, is_dev);
+}
+
+scl_status scl_get_populations(scl_lattice L, double* out, int32_t is_dev) {
+  if (!L || !out) return fail(SCL_E_INVALID, "bad arguments");
+  scl_status s = ready(L);
+  if (s != SCL_OK) return s;
+  const size_t n = (size_t)L->Q * L->cells;
+  double* dst = out;
+  if (!is_dev) HIPCHK(hipMalloc(&dst, n * sizeof(double)));
+  std::vector<DomDev> doms = host_doms(L);
+  for (int k = 0; k < L->ndom; ++k) {
+    const long long c = (long long)L->nx[k] * L->ny[k] * L->nz[k];
+    const unsigned nb = blocks_for(c, 256);
+#define GETP(VS, S) hipLaunchKernelGGL((k_get_pops<VS, S>), dim3(nb), dim3(256), 0, L->stream, (const S*)L->A, dst, doms[k])
+    if (L->vs == SCL_D2Q9) {
+      if (L->prec == SCL_FP64) GETP(0, double); else if (L->prec == SCL_FP16S_FP32) GETP(0, _Float16); else GETP(0, float);
+    } else {
+      if (L->prec == SCL_FP64) GETP(1, double); else if (L->prec == SCL_FP16S_FP32) GETP(1, _Float16); else GETP(1, float);
+    }
+#undef GETP
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipStreamSynchronize(L->stream));
+  if (!is_dev) {
+    HIPCHK(hipMemcpy(out, dst, n * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipFree(dst));
+  }
+  return SCL_OK;
+}
+
+scl_status scl_set_populations(scl_lattice L, const double* in, int32_t is_dev) {
+  if (!L || !in) return fail(SCL_E_INVALID, "bad arguments");
+  if (!L->have_state) return fail(SCL_E_STATE, "scl_init_density has not been called");
+  scl_status s = sync_params(L);
+  if (s != SCL_OK) return s;
+  const size_t n = (size_t)L->Q * L->cells;
+  const double* src = in;
+  double* tmp = nullptr;
+  if (!is_dev) {
+    HIPCHK(hipMalloc(&tmp, n * sizeof(double)));
+    HIPCHK(hipMemcpy(tmp, in, n * sizeof(double), hipMemcpyHostToDevice));
+    src = tmp;
+  }
+  std::vector<DomDev> doms = host_doms(L);
+  for (int k = 0; k < L->ndom; ++k) {
+    const long long c = (long long)L->nx[k] * L->ny[k] * L->nz[k];
+    const unsigned nb = blocks_for(c, 256);
+#define SETP(VS, S) hipLaunchKernelGGL((k_set_pops<VS, S>), dim3(nb), dim3(256), 0, L->stream, (S*)L->A, src, doms[k])
+    if (L->vs == SCL_D2Q9) {
+      if (L->prec == SCL_FP64) SETP(0, double); else if (L->prec == SCL_FP16S_FP32) SETP(0, _Float16); else SETP(0, float);
+    } else {
+      if (L->prec == SCL_FP64) SETP(1, double); else if (L->prec == SCL_FP16S_FP32) SETP(1, _Float16); else SETP(1, float);
+    }
+#undef SETP
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipStreamSynchronize(L->stream));
+  if (tmp) HIPCHK(hipFree(tmp));
+  drop_graph(L);
+  return SCL_OK;
+}
+
+scl_status scl_reduce_conserved(scl_lattice L, double* mass, double* momentum) {
+  if (!L || !mass) return fail(SCL_E_INVALID, "bad arguments");
+  scl_status s = compute_fields(L, true);
+  if (s != SCL_OK) return s;
+  const int nv = 1 + L->d;
+  double* d_out = nullptr;
+  HIPCHK(hipMalloc(&d_out, sizeof(double) * nv * L->ndom));
+  for (int k = 0; k < L->ndom; ++k) {
+    const long long c = (long long)L->nx[k] * L->ny[k] * L->nz[k];
+    const long long chunk = 4096;
+    const int nb = (int)((c + chunk - 1) / chunk);
+    if ((size_t)nb * nv > L->part_cap) {
+      if (L->d_part) HIPCHK(hipFree(L->d_part));
+      L->part_cap = (size_t)nb * nv;
+      HIPCHK(hipMalloc(&L->d_part, sizeof(double) * L->part_cap));
+    }
+    if (L->d == 2)
+      hipLaunchKernelGGL(k_reduce_partial<2>, dim3(nb), dim3(RED_NT), 0, L->stream, L->d_n, L->d_j, L->d_F, L->d_part, L->cells, L->off[k], c, chunk);
+    else
+      hipLaunchKernelGGL(k_reduce_partial<3>, dim3(nb), dim3(RED_NT), 0, L->stream, L->d_n, L->d_j, L->d_F, L->d_part, L->cells, L->off[k], c, chunk);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_NT), 0, L->stream, (const double*)L->d_part, nb, nv, d_out + (size_t)k * nv);
+    HIPCHK(hipGetLastError());
+  }
+  std::vector<double> h((size_t)nv * L->ndom);
+  HIPCHK(hipMemcpyAsync(h.data(), d_out, h.size() * sizeof(double), hipMemcpyDeviceToHost, L->stream));
+  HIPCHK(hipStreamSynchronize(L->stream));
+  HIPCHK(hipFree(d_out));
+  bool finite = true;
+  for (int k = 0; k < L->ndom; ++k) {
+    mass[k] = h[(size_t)k * nv];
+    finite = finite && std::isfinite(mass[k]);
+    if (momentum)
+      for (int q = 0; q < L->d; ++q) momentum[(size_t)k * L->d + q] = h[(size_t)k * nv + 1 + q];
+  }
+  if (!finite) return fail(SCL_E_NONFINITE, "mass is not finite: the run diverged");
+  return SCL_OK;
+}
+
+scl_status scl_get_pressure_tensor(scl_lattice L, double* out, int32_t is_dev) {
+  if (!L || !out) return fail(SCL_E_INVALID, "bad arguments");
+  if (L->d != 2) return fail(SCL_E_UNSUPPORTED, "the lattice pressure tensor is implemented for D2Q9 only");
+  scl_status s = compute_fields(L, false);
+  if (s != SCL_OK) return s;
+  std::vector<DomDev> doms = host_doms(L);
+  VecTable tab = full_table(L);
+  int slot5 = -1;
+  for (int q = 0; q < SET2N[L->set]; ++q)
+    if (SET2[L->set][q] == 5) slot5 = q;
+  for (int k = 0; k < L->ndom; ++k) {
+    const long long c = (long long)L->nx[k] * L->ny[k];
+    hipLaunchKernelGGL(k_ptensor2d, dim3(blocks_for(c, 256)), dim3(256), 0, L->stream, (const double*)L->d_n,
+                       (const double*)L->d_psi, L->d_tmp, L->cells, doms[k], tab, slot5);
+    HIPCHK(hipGetLastError());
+  }
+  return copy_out(L, out, L->d_tmp, (size_t)3 * L->cells, is_dev);
+}
+
+scl_status scl_droplet_observables(scl_lattice L, const int32_t* center, const int8_t* is_bubble, double* out) {
+  if (!L || !center || !out) return fail(SCL_E_INVALID, "bad arguments");
+  if (L->d != 2) return fail(SCL_E_UNSUPPORTED, "droplet observables are implemented for D2Q9 only");
+  for (int k = 0; k < L->ndom; ++k) {
+    if (L->nx[k] != L->ny[k]) return fail(SCL_E_INVALID, "droplet observables need square domains");
+    if (center[2 * k] < 0 || center[2 * k] >= L->nx[k] || center[2 * k + 1] < 0 || center[2 * k + 1] >= L->ny[k])
+      return fail(SCL_E_INVALID, "centre outside the domain");
+  }
+  std::vector<double> P((size_t)3 * L->cells);
+  scl_status s = scl_get_pressure_tensor(L, P.data(), 0);
+  if (s != SCL_OK) return s;
+  std::vector<double> n((size_t)L->cells);
+  HIPCHK(hipMemcpy(n.data(), L->d_n, n.size() * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<double> mass(L->ndom);
+  s = scl_reduce_conserved(L, mass.data(), nullptr);
+  if (s != SCL_OK) return s;
+  const long long C = L->cells;
+  for (int k = 0; k < L->ndom; ++k) {
+    const int Ls = L->nx[k], cx = center[2 * k], cy = center[2 * k + 1];
+    const long long o = L->off[k];
+    auto at = [&](int plane, int x, int y) { return P[(size_t)(plane * C + o + (long long)wrapi(y, Ls) * Ls + wrapi(x, Ls))]; };
+    const double Pc = 0.5 * (at(0, cx, cy) + at(1, cx, cy));
+    const double Po = 0.5 * (at(0, 0, 0) + at(1, 0, 0));
+    const double dP = Pc - Po;
+    const int Rm = Ls / 2;
+    double Cd = 0;
+    for (int sg = -1; sg <= 1; sg += 2) {
+      double sum = 0;
+      for (int r = 0; r <= Rm; ++r) {
+        double g = r * (Po - at(1, cx + sg * r, cy));
+        if (r == 0 || r == Rm) g *= 0.5;
+        sum += g;
+      }
+      Cd += 0.5 * sum;
+    }
+    const double Rs = std::sqrt(2.0 * Cd / dP);
+    const bool bub = is_bubble && is_bubble[k];
+    const double sig = (bub ? -1.0 : 1.0) * dP * Rs;
+    const double nin = n[(size_t)(o + (long long)cy * Ls + cx)];
+    const double nout = n[(size_t)o];
+    const double Re = std::sqrt((mass[k] - (double)Ls * Ls * nout) / (M_PI * (nin - nout)));
+    double* r6 = out + (size_t)6 * k;
+    r6[0] = dP; r6[1] = Cd; r6[2] = Rs; r6[3] = sig; r6[4] = Re; r6[5] = Re - Rs;
+  }
+  return SCL_OK;
+}
+
+scl_status scl_set_tiling(scl_lattice L, int32_t strip, int32_t seg) {
+  if (!L || strip < 0 || seg < 0) return fail(SCL_E_INVALID, "bad tiling");
+  if (L->d == 2) {
+    if (strip != 0 && strip != 64 && strip != 128 && strip != 256) return fail(SCL_E_INVALID, "2D strip must be 64, 128 or 256");
+    if (strip) L->strip = strip;
+    if (seg) L->seg = seg;
+  } else {
+    if (strip > 3) return fail(SCL_E_INVALID, "3D tile index must be 1 (32x8), 2 (32x16) or 3 (32x32)");
+    if (strip == 3 && L->prec == SCL_FP64) return fail(SCL_E_INVALID, "the 32x32 tile is for float arithmetic");
+    if (strip) L->tile3 = strip;
+    if (seg) L->seg3 = seg;
+  }
+  L->dirty_items = true;
+  drop_graph(L);
+  return SCL_OK;
+}
+
+scl_status scl_get_tiling(scl_lattice L, int32_t* strip, int32_t* seg) {
+  if (!L || !strip || !seg) return fail(SCL_E_INVALID, "bad arguments");
+  *strip = L->d == 2 ? L->strip : L->tile3;
+  *seg = L->d == 2 ? L->seg : L->seg3;
+  return SCL_OK;
+}
+
+scl_status scl_set_graph_steps(scl_lattice L, int32_t k) {
+  if (!L || k < 0 || (k % 2) != 0) return fail(SCL_E_INVALID, "graph length must be even and >= 0");
+  L->graph_k = k;
+  drop_graph(L);
+  return SCL_OK;
+}
+
+scl_status scl_tune(scl_lattice L, const char* cache_path) {
+  if (!L) return fail(SCL_E_INVALID, "bad arguments");
+  scl_status s = ready(L);
+  if (s != SCL_OK) return s;
+  hipDeviceProp_t prop;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  std::ostringstream key;
+  key << prop.gcnArchName << " vs" << (int)L->vs << " reach" << stencil_reach(L) << " prec" << (int)L->prec;
+  for (int k = 0; k < L->ndom; ++k) key << " " << L->nx[k] << "x" << L->ny[k] << "x" << L->nz[k];
+  const std::string ks = key.str();
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      const size_t bar = line.rfind('|');
+      if (bar == std::string::npos || line.substr(0, bar) != ks) continue;
+      int a = 0, b = 0;
+      if (std::sscanf(line.c_str() + bar + 1, "%d %d", &a, &b) == 2) return scl_set_tiling(L, a, b);
+    }
+  }
+  std::vector<std::pair<int, int>> cands;
+  if (L->d == 2) {
+    for (int st : {64, 128, 256})
+      for (int sg : {16, 32, 64, 128, 256}) cands.push_back({st, sg});
+  } else {
+    for (int t : {1, 2, 3}) {
+      if (t == 3 && L->prec == SCL_FP64) continue;
+      for (int sg : {8, 16, 32, 64}) cands.push_back({t, sg});
+    }
+  }
+  const int saved_graph = L->graph_k;
+  L->graph_k = 0;
+  double best = 1e30;
+  std::pair<int, int> bc = cands[0];
+  const int reps = 4;
+  for (auto c : cands) {
+    s = scl_set_tiling(L, c.first, c.second);
+    if (s != SCL_OK) return s;
+    double ms = 0;
+    s = scl_step_timed(L, 2, &ms);  // warm-up (and item upload)
+    if (s != SCL_OK) return s;
+    s = scl_step_timed(L, reps, &ms);
+    if (s != SCL_OK) return s;
+    if (ms < best) { best = ms; bc = c; }
+  }
+  L->graph_k = saved_graph;
+  s = scl_set_tiling(L, bc.first, bc.second);
+  if (s != SCL_OK) return s;
+  if (cache_path) {
+    std::ofstream o(cache_path, std::ios::app);
+    o << ks << "|" << bc.first << " " << bc.second << "\n";
+  }
+  return SCL_OK;
+}
+
+}  // extern "C"

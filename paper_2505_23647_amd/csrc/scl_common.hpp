@@ -1,0 +1,162 @@
+// Shared definitions of the libscl kernels: velocity sets, forcing-stencil half lists,
+// per-domain parameters, work items and small device helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <type_traits>
+#include <utility>
+
+namespace scl {
+
+constexpr int MAX_SHELLS = 8;   // weight slots per domain
+constexpr double CS2 = 1.0 / 3.0;
+
+// ------------------------------------------------------------------ velocity sets
+// D2Q9 order: rest, (1,0), (0,1), (-1,0), (0,-1), (1,1), (-1,1), (-1,-1), (1,-1).
+// D3Q19 order: rest, +x, -x, +y, -y, +z, -z, then (+-1,+-1,0), (+-1,0,+-1), (0,+-1,+-1).
+template <int VS> struct Vel;
+
+template <> struct Vel<0> {
+  static constexpr int Q = 9, D = 2;
+  __host__ __device__ static constexpr int cx(int i) {
+    constexpr int a[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    return a[i];
+  }
+  __host__ __device__ static constexpr int cy(int i) {
+    constexpr int a[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    return a[i];
+  }
+  __host__ __device__ static constexpr int cz(int) { return 0; }
+  __host__ __device__ static constexpr double w(int i) {
+    return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+  }
+};
+
+template <> struct Vel<1> {
+  static constexpr int Q = 19, D = 3;
+  __host__ __device__ static constexpr int cx(int i) {
+    constexpr int a[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    return a[i];
+  }
+  __host__ __device__ static constexpr int cy(int i) {
+    constexpr int a[19] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
+    return a[i];
+  }
+  __host__ __device__ static constexpr int cz(int i) {
+    constexpr int a[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
+    return a[i];
+  }
+  __host__ __device__ static constexpr double w(int i) {
+    return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+  }
+};
+
+// ------------------------------------------------------------------ forcing-stencil half lists
+// The force sums W_a psi(x + e_a) e_a over +-pairs; each list holds one vector of every pair
+// (the other is its negative) and the weight slot of its shell. A shell set names a
+// compile-time superset of shells; a domain's weights for absent shells are zero.
+//   2D set 0: {1,2}             (8 vectors, reach 1)
+//   2D set 1: {1,2,4,5,8}       (24 vectors, reach 2)
+//   3D set 0: {1,2,3}           (26 vectors, reach 1)
+//   3D set 1: {1,2,3,4,5,6,8}   (92 vectors, reach 2)
+struct HalfVec { int8_t x, y, z, slot; };
+
+template <int D, int SET> struct Shells;
+
+template <> struct Shells<2, 0> {
+  static constexpr int R = 1, NH = 4, NS = 2;
+  __host__ __device__ static constexpr int code(int s) { constexpr int c[2] = {1, 2}; return c[s]; }
+  __host__ __device__ static constexpr HalfVec h(int k) {
+    constexpr HalfVec v[4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {1, 1, 0, 1}, {-1, 1, 0, 1}};
+    return v[k];
+  }
+};
+
+template <> struct Shells<2, 1> {
+  static constexpr int R = 2, NH = 12, NS = 5;
+  __host__ __device__ static constexpr int code(int s) { constexpr int c[5] = {1, 2, 4, 5, 8}; return c[s]; }
+  __host__ __device__ static constexpr HalfVec h(int k) {
+    constexpr HalfVec v[12] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {1, 1, 0, 1}, {-1, 1, 0, 1},
+                               {2, 0, 0, 2}, {0, 2, 0, 2}, {2, 1, 0, 3}, {1, 2, 0, 3},
+                               {-1, 2, 0, 3}, {-2, 1, 0, 3}, {2, 2, 0, 4}, {-2, 2, 0, 4}};
+    return v[k];
+  }
+};
+
+// 3D half lists are generated on the host into constant tables of this size.
+constexpr int MAX_HALF_3D = 46;
+
+// ------------------------------------------------------------------ per-domain parameters
+struct DomDev {
+  long long off;        // first site of the domain in the concatenated site order
+  int nx, ny, nz;
+  int psi_kind;         // 0 exp(-1/n), 1 (n/(eps+n))^(1/eps), 2 1 - exp(-n)
+  double omega;         // 1 / tau
+  double kappa;         // 1 - 1/(2 tau)
+  double gpre;          // -G c_s^2 (force prefactor)
+  double eps;           // pseudopotential parameter
+  double inv_eps;       // 1 / eps
+  double rho0;          // storage shift (0 when not shifted)
+  double W[MAX_SHELLS]; // weight of each shell slot of the compile-time set
+};
+
+// A workgroup's share of one step: a strip of output columns [x0, x0 + width) of domain dom
+// (2D: rows [y0, y1); 3D: additionally output rows [y0, y0 + tile) and planes [z0, z1)).
+struct WorkItem {
+  int dom;
+  int x0;
+  int y0, y1;
+  int z0, z1;
+};
+
+// Optional recording of the macroscopic fields of every site a step updates (used by the
+// adjoint's recompute pass): n, j (d values), F (d values), each a [cells] plane.
+template <class M> struct MacroRec {
+  M* n;
+  M* j;   // d planes
+  M* F;   // d planes
+  long long cells;
+};
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I = 0 .. N-1, so that register
+// arrays indexed by I stay in registers.
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F> __device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+__host__ __device__ inline int wrapi(int a, int n) {
+  int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+// ------------------------------------------------------------------ pseudopotential
+template <class M> __device__ inline M psi_eval(M n, int kind, M eps, M inv_eps);
+
+template <> __device__ inline float psi_eval<float>(float n, int kind, float eps, float inv_eps) {
+  if (kind == 0) return expf(-1.0f / n);
+  if (kind == 1) return powf(n / (eps + n), inv_eps);
+  return 1.0f - expf(-n);
+}
+template <> __device__ inline double psi_eval<double>(double n, int kind, double eps, double inv_eps) {
+  if (kind == 0) return exp(-1.0 / n);
+  if (kind == 1) return pow(n / (eps + n), inv_eps);
+  return 1.0 - exp(-n);
+}
+
+// dpsi/dn
+template <class M> __device__ inline M dpsi_eval(M n, M psi, int kind, M eps) {
+  if (kind == 0) return psi / (n * n);
+  if (kind == 1) return psi / (n * (eps + n));
+  return M(1) - psi;
+}
+
+// ------------------------------------------------------------------ storage conversion
+template <class S, class M> __device__ inline M ld(const S* p) { return static_cast<M>(*p); }
+template <class S, class M> __device__ inline void st(S* p, M v) { *p = static_cast<S>(v); }
+
+}  // namespace scl

@@ -1,0 +1,178 @@
+"""Python face of libscl: a handle class whose methods map one-to-one onto the C ABI.
+
+Host arrays are numpy; device arrays may be passed as torch tensors on the GPU (their
+data pointer is handed to the library with is_device_ptr = 1). Nothing here computes.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib as B
+from ._lib import check, lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _is_torch_cuda(a):
+    return hasattr(a, "is_cuda") and a.is_cuda
+
+
+def velocity_set(vs: int):
+    xi = np.zeros((19, 3), dtype=np.int32)
+    w = np.zeros(19)
+    q = lib().scl_velocity_set(vs, _dptr(xi), _dptr(w))
+    if q < 0:
+        raise ValueError("unknown velocity set")
+    return xi[:q].copy(), w[:q].copy()
+
+
+class Lattice:
+    """A batch of independent periodic domains (one or more) on the GPU.
+
+    dims: list of (nx, ny) or (nx, ny, nz); D2Q9 for 2D, D3Q19 for 3D.
+    stream: a hipStream_t handle as int (e.g. torch.cuda.current_stream().cuda_stream) or None.
+    """
+
+    def __init__(self, dims, precision=B.SCL_FP64, stream=None):
+        dims = [tuple(int(v) for v in d) for d in dims]
+        self.d = len(dims[0])
+        if any(len(d) != self.d for d in dims):
+            raise ValueError("all domains must have the same dimension")
+        self.vs = B.SCL_D2Q9 if self.d == 2 else B.SCL_D3Q19
+        self.precision = precision
+        self.dims = [d if self.d == 3 else d + (1,) for d in dims]
+        self.ndom = len(dims)
+        self.cells_per_dom = [int(np.prod(d)) for d in self.dims]
+        self.cells = sum(self.cells_per_dom)
+        self.offsets = np.concatenate([[0], np.cumsum(self.cells_per_dom)[:-1]]).astype(np.int64)
+        arr = np.ascontiguousarray(np.array(self.dims, dtype=np.int32).reshape(-1))
+        h = ctypes.c_void_p()
+        check(lib().scl_create(self.vs, precision, self.ndom, _dptr(arr), ctypes.c_void_p(stream or 0),
+                               ctypes.byref(h)))
+        self.h = h
+        self.xi, self.w = velocity_set(self.vs)
+        self.Q = len(self.w)
+
+    # ------------------------------------------------------------------ lifetime
+    def close(self):
+        if getattr(self, "h", None):
+            lib().scl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ setup
+    def set_physics(self, tau, G, psi_kind=B.SCL_PSI_EXP, psi_param=None):
+        tau = np.ascontiguousarray(np.broadcast_to(np.asarray(tau, dtype=np.float64), (self.ndom,)))
+        G = np.ascontiguousarray(np.broadcast_to(np.asarray(G, dtype=np.float64), (self.ndom,)))
+        pp = None
+        if psi_param is not None:
+            pp = np.ascontiguousarray(np.broadcast_to(np.asarray(psi_param, dtype=np.float64), (self.ndom,)))
+        check(lib().scl_set_physics(self.h, _dptr(tau), _dptr(G), psi_kind, _dptr(pp) if pp is not None else None))
+        return self
+
+    def set_stencil(self, codes, W):
+        codes = np.ascontiguousarray(codes, dtype=np.int32)
+        W = np.asarray(W, dtype=np.float64)
+        if W.ndim == 1:
+            W = np.tile(W, (self.ndom, 1))
+        W = np.ascontiguousarray(W)
+        check(lib().scl_set_stencil(self.h, len(codes), _dptr(codes), _dptr(W)))
+        return self
+
+    def init_density(self, n0):
+        if _is_torch_cuda(n0):
+            check(lib().scl_init_density(self.h, ctypes.c_void_p(n0.data_ptr()), 1))
+        else:
+            n0 = np.ascontiguousarray(np.asarray(n0, dtype=np.float64).reshape(-1))
+            if n0.size != self.cells:
+                raise ValueError("n0 has the wrong size")
+            check(lib().scl_init_density(self.h, _dptr(n0), 0))
+        return self
+
+    # ------------------------------------------------------------------ stepping
+    def step(self, nsteps=1):
+        check(lib().scl_step(self.h, int(nsteps)))
+        return self
+
+    def step_timed(self, nsteps):
+        ms = ctypes.c_double()
+        check(lib().scl_step_timed(self.h, int(nsteps), ctypes.byref(ms)))
+        return ms.value
+
+    def step_count(self):
+        v = ctypes.c_int64()
+        check(lib().scl_get_step_count(self.h, ctypes.byref(v)))
+        return v.value
+
+    def set_tiling(self, strip=0, seg=0):
+        check(lib().scl_set_tiling(self.h, int(strip), int(seg)))
+        return self
+
+    def get_tiling(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().scl_get_tiling(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def tune(self, cache_path=None):
+        check(lib().scl_tune(self.h, cache_path.encode() if cache_path else None))
+        return self.get_tiling()
+
+    def set_graph_steps(self, k):
+        check(lib().scl_set_graph_steps(self.h, int(k)))
+        return self
+
+    # ------------------------------------------------------------------ readouts
+    def _get(self, fn, count):
+        out = np.empty(count)
+        check(fn(self.h, _dptr(out), 0))
+        return out
+
+    def density(self):
+        return self._get(lib().scl_get_density, self.cells)
+
+    def velocity(self):
+        return self._get(lib().scl_get_velocity, self.d * self.cells).reshape(self.d, self.cells)
+
+    def force(self):
+        return self._get(lib().scl_get_force, self.d * self.cells).reshape(self.d, self.cells)
+
+    def populations(self):
+        """Populations f_i(x, t) as doubles, domain by domain [Q][cells_of_domain] blocks."""
+        return self._get(lib().scl_get_populations, self.Q * self.cells)
+
+    def domain_populations(self, k):
+        p = self.populations()
+        o, c = int(self.offsets[k]) * self.Q, self.cells_per_dom[k]
+        return p[o:o + self.Q * c].reshape(self.Q, c)
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1))
+        check(lib().scl_set_populations(self.h, _dptr(f), 0))
+        return self
+
+    def pressure_tensor(self):
+        return self._get(lib().scl_get_pressure_tensor, 3 * self.cells).reshape(3, self.cells)
+
+    def reduce_conserved(self):
+        mass = np.empty(self.ndom)
+        mom = np.empty((self.ndom, self.d))
+        check(lib().scl_reduce_conserved(self.h, _dptr(mass), _dptr(mom)))
+        return mass, mom
+
+    def droplet_observables(self, centers, is_bubble=None):
+        c = np.ascontiguousarray(np.asarray(centers, dtype=np.int32).reshape(self.ndom, 2))
+        b = None
+        if is_bubble is not None:
+            b = np.ascontiguousarray(np.asarray(is_bubble, dtype=np.int8).reshape(self.ndom))
+        out = np.empty((self.ndom, 6))
+        check(lib().scl_droplet_observables(self.h, _dptr(c), _dptr(b) if b is not None else None, _dptr(out)))
+        return out
