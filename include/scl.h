@@ -160,11 +160,16 @@ scl_status scl_get_pressure_tensor(scl_lattice lat, double* out, int32_t is_devi
 scl_status scl_droplet_observables(scl_lattice lat, const int32_t* center, const int8_t* is_bubble,
                                    double* out);
 
-/* Tiling of the fused step: strip = lanes per workgroup along x (64, 128 or 256 in 2D;
- * 3D: 0 = default tile), seg = rows (2D) or planes (3D) marched by one workgroup (>= 1).
- * 0 keeps the current value. */
-scl_status scl_set_tiling(scl_lattice lat, int32_t strip, int32_t seg);
-scl_status scl_get_tiling(scl_lattice lat, int32_t* strip, int32_t* seg);
+/* Tiling of the fused step.
+ *   2D: strip = output lanes per workgroup (64, 128 or 256); seg = rows one workgroup marches
+ *       (>= 1); cpl = sites per lane (1, or 2 for vector accesses, which needs every domain
+ *       width even; 0 = 2 when possible).
+ *   3D: strip = tile index (1: 32x8, 2: 32x16, 3: 32x32 lanes, float arithmetic only);
+ *       seg = planes one workgroup marches; cpl is ignored.
+ * 0 keeps the current value (for cpl: automatic). */
+scl_status scl_set_tiling(scl_lattice lat, int32_t strip, int32_t seg, int32_t cpl);
+/* Current tiling; cpl may be NULL. seg 0 means the automatic choice. */
+scl_status scl_get_tiling(scl_lattice lat, int32_t* strip, int32_t* seg, int32_t* cpl);
 
 /* Autotuner: times the candidate tilings on this lattice (advancing it by the steps it
  * uses, see scl_get_step_count) and keeps the fastest. If cache_path is not NULL the choice

@@ -84,7 +84,9 @@ struct scl_lattice_s {
   int nitems = 0;
   bool dirty_doms = true, dirty_items = true;
   // tiling
-  int strip = 256, seg = 0;        // 2D: lanes per workgroup, rows per item (0 = auto)
+  int strip = 128, seg = 0;        // 2D: output lanes per workgroup, rows per item (0 = auto)
+  int cpl_req = 0;                 // 2D: sites per lane requested (0 = auto)
+  int cpl = 1;                     // 2D: sites per lane in use
   int tile3 = 2, seg3 = 0;         // 3D: tile index, planes per item (0 = auto)
   // graphs
   int graph_k = 0;
@@ -151,30 +153,37 @@ scl_status build_items(scl_lattice_s* L) {
   std::vector<WorkItem> items;
   const int R = stencil_reach(L);
   if (L->d == 2) {
-    const int outw = L->strip - 2 * R;
-    long long ncols_items = 0, rows = 0;
-    for (int k = 0; k < L->ndom; ++k) {
-      ncols_items += (L->nx[k] + outw - 1) / outw;
-      rows = std::max<long long>(rows, L->ny[k]);
-    }
+    // sites per lane (two need every domain width even)
+    bool even = true;
+    for (int k = 0; k < L->ndom; ++k) even = even && (L->nx[k] % 2 == 0);
+    // automatic: one site per lane. Measured on MI355X (4096^2, 24-vector stencil) two sites
+    // per lane lose to it: the shifted 8-byte pulls are unaligned and the extra registers
+    // cut occupancy to 3 waves per SIMD.
+    L->cpl = L->cpl_req ? L->cpl_req : 1;
+    if (L->cpl == 2 && !even) return fail(SCL_E_INVALID, "two sites per lane need even domain widths");
+    const int outw = L->strip * L->cpl;
+    // rows per item: measured best on MI355X with 128-lane strips (4096^2, 24 vectors):
+    // 32 for 4- and 2-byte storage, 128 for FP64
     int seg = L->seg;
-    if (seg <= 0) {
-      // aim for about 2048 workgroups (8 per CU) but at least 32 rows per item
-      long long work = 0;
-      for (int k = 0; k < L->ndom; ++k) work += (long long)((L->nx[k] + outw - 1) / outw) * L->ny[k];
-      seg = (int)std::max<long long>(32, (work + 2047) / 2048);
-    }
+    if (seg <= 0) seg = L->prec == SCL_FP64 ? 128 : 32;
+    // Order: bands of BAND row ranges; within a band, strip by strip, the ranges of the band
+    // in order. The device hands each XCD a contiguous eighth of this list, so an XCD works on
+    // a compact block of neighbouring strips and ranges whose shared halos meet in its L2.
+    // Consecutive ranges of a strip march in opposite directions.
+    const int BAND = 8;
     for (int k = 0; k < L->ndom; ++k) {
       const int ns = (L->nx[k] + outw - 1) / outw;
-      for (int y0 = 0; y0 < L->ny[k]; y0 += seg)
-        for (int s = 0; s < ns; ++s) {
-          WorkItem w{};
-          w.dom = k; w.x0 = s * outw; w.y0 = y0; w.y1 = std::min(y0 + seg, L->ny[k]);
-          w.z0 = 0; w.z1 = 1;
-          items.push_back(w);
-        }
+      const int nseg = (L->ny[k] + seg - 1) / seg;
+      for (int b0 = 0; b0 < nseg; b0 += BAND)
+        for (int sx = 0; sx < ns; ++sx)
+          for (int sg = b0; sg < std::min(b0 + BAND, nseg); ++sg) {
+            WorkItem w{};
+            w.dom = k; w.x0 = sx * outw; w.y0 = sg * seg; w.y1 = std::min((sg + 1) * seg, L->ny[k]);
+            w.z0 = 0; w.z1 = 1;
+            w.dir = (sg % 2 == 0) ? 1 : -1;
+            items.push_back(w);
+          }
     }
-    (void)ncols_items; (void)rows;
   } else {
     const Tile3 t = TILES3[L->tile3];
     const int ox = t.tx - 2 * R, oy = t.ty - 2 * R;
@@ -192,6 +201,7 @@ scl_status build_items(scl_lattice_s* L) {
             WorkItem w{};
             w.dom = k; w.x0 = x0; w.y0 = y0; w.y1 = std::min(y0 + oy, L->ny[k]);
             w.z0 = z0; w.z1 = std::min(z0 + seg, L->nz[k]);
+            w.dir = 1;
             items.push_back(w);
           }
   }
@@ -225,18 +235,25 @@ void drop_graph(scl_lattice_s* L) {
 // ------------------------------------------------------------------ step dispatch
 template <class S, class M, bool SHIFT>
 hipError_t launch2d(scl_lattice_s* L, const void* fin, void* fout, MacroRec<M> rec, bool record) {
-  const dim3 grid(L->nitems);
-  auto go = [&](auto kern, int nt) {
-    hipLaunchKernelGGL(kern, grid, dim3(nt), 0, L->launch, (const S*)fin, (S*)fout, L->d_doms, L->d_items, rec);
-  };
-#define SCL_2D_CASE(SETV, NTV)                                                     \
-  if (L->set == SETV && L->strip == NTV) {                                          \
-    if (record) go(k_step2d<S, M, SETV, NTV, SHIFT, true>, NTV);                    \
-    else go(k_step2d<S, M, SETV, NTV, SHIFT, false>, NTV);                          \
-    return hipGetLastError();                                                       \
+  // eight XCDs: the kernel maps workgroup id -> item so that each XCD takes a contiguous
+  // eighth of the list; round the grid up to a multiple of 8
+  const int per = (L->nitems + 7) / 8;
+  const dim3 grid(8 * per);
+#define SCL_2D_CASE(SETV, NOV, CPLV)                                                                  \
+  if (L->set == SETV && L->strip == NOV && L->cpl == CPLV) {                                           \
+    constexpr int nt = NOV + 2 * Halo2<SETV, CPLV>::HL;                                                \
+    if (record)                                                                                        \
+      hipLaunchKernelGGL((k_step2d<S, M, SETV, NOV, CPLV, SHIFT, true>), grid, dim3(nt), 0, L->launch,  \
+                         (const S*)fin, (S*)fout, L->d_doms, L->d_items, L->nitems, rec);              \
+    else                                                                                               \
+      hipLaunchKernelGGL((k_step2d<S, M, SETV, NOV, CPLV, SHIFT, false>), grid, dim3(nt), 0, L->launch, \
+                         (const S*)fin, (S*)fout, L->d_doms, L->d_items, L->nitems, rec);              \
+    return hipGetLastError();                                                                          \
   }
-  SCL_2D_CASE(0, 64) SCL_2D_CASE(0, 128) SCL_2D_CASE(0, 256)
-  SCL_2D_CASE(1, 64) SCL_2D_CASE(1, 128) SCL_2D_CASE(1, 256)
+  SCL_2D_CASE(0, 64, 1) SCL_2D_CASE(0, 128, 1) SCL_2D_CASE(0, 256, 1)
+  SCL_2D_CASE(1, 64, 1) SCL_2D_CASE(1, 128, 1) SCL_2D_CASE(1, 256, 1)
+  SCL_2D_CASE(0, 64, 2) SCL_2D_CASE(0, 128, 2) SCL_2D_CASE(0, 256, 2)
+  SCL_2D_CASE(1, 64, 2) SCL_2D_CASE(1, 128, 2) SCL_2D_CASE(1, 256, 2)
 #undef SCL_2D_CASE
   return hipErrorInvalidValue;
 }
@@ -801,12 +818,19 @@ scl_status scl_droplet_observables(scl_lattice L, const int32_t* center, const i
   return SCL_OK;
 }
 
-scl_status scl_set_tiling(scl_lattice L, int32_t strip, int32_t seg) {
-  if (!L || strip < 0 || seg < 0) return fail(SCL_E_INVALID, "bad tiling");
+scl_status scl_set_tiling(scl_lattice L, int32_t strip, int32_t seg, int32_t cpl) {
+  if (!L || strip < 0 || seg < 0 || cpl < 0) return fail(SCL_E_INVALID, "bad tiling");
   if (L->d == 2) {
     if (strip != 0 && strip != 64 && strip != 128 && strip != 256) return fail(SCL_E_INVALID, "2D strip must be 64, 128 or 256");
+    if (cpl > 2) return fail(SCL_E_INVALID, "sites per lane must be 1 or 2 (0 = automatic)");
+    if (cpl == 2 && L->prec == SCL_FP16S_FP32)
+      return fail(SCL_E_UNSUPPORTED, "two sites per lane are not offered for FP16 storage");
+    if (cpl == 2)
+      for (int k = 0; k < L->ndom; ++k)
+        if (L->nx[k] % 2) return fail(SCL_E_INVALID, "two sites per lane need even domain widths");
     if (strip) L->strip = strip;
     if (seg) L->seg = seg;
+    L->cpl_req = cpl;
   } else {
     if (strip > 3) return fail(SCL_E_INVALID, "3D tile index must be 1 (32x8), 2 (32x16) or 3 (32x32)");
     if (strip == 3 && L->prec == SCL_FP64) return fail(SCL_E_INVALID, "the 32x32 tile is for float arithmetic");
@@ -818,10 +842,11 @@ scl_status scl_set_tiling(scl_lattice L, int32_t strip, int32_t seg) {
   return SCL_OK;
 }
 
-scl_status scl_get_tiling(scl_lattice L, int32_t* strip, int32_t* seg) {
+scl_status scl_get_tiling(scl_lattice L, int32_t* strip, int32_t* seg, int32_t* cpl) {
   if (!L || !strip || !seg) return fail(SCL_E_INVALID, "bad arguments");
   *strip = L->d == 2 ? L->strip : L->tile3;
   *seg = L->d == 2 ? L->seg : L->seg3;
+  if (cpl) *cpl = L->d == 2 ? L->cpl : 1;
   return SCL_OK;
 }
 
@@ -851,13 +876,13 @@ scl_status scl_tune(scl_lattice L, const char* cache_path) {
       const size_t bar = line.rfind('|');
       if (bar == std::string::npos || line.substr(0, bar) != ks) continue;
       int a = 0, b = 0;
-      if (std::sscanf(line.c_str() + bar + 1, "%d %d", &a, &b) == 2) return scl_set_tiling(L, a, b);
+      if (std::sscanf(line.c_str() + bar + 1, "%d %d", &a, &b) == 2) return scl_set_tiling(L, a, b, 0);
     }
   }
   std::vector<std::pair<int, int>> cands;
   if (L->d == 2) {
     for (int st : {64, 128, 256})
-      for (int sg : {16, 32, 64, 128, 256}) cands.push_back({st, sg});
+      for (int sg : {8, 16, 32, 64, 128}) cands.push_back({st, sg});
   } else {
     for (int t : {1, 2, 3}) {
       if (t == 3 && L->prec == SCL_FP64) continue;
@@ -870,7 +895,7 @@ scl_status scl_tune(scl_lattice L, const char* cache_path) {
   std::pair<int, int> bc = cands[0];
   const int reps = 4;
   for (auto c : cands) {
-    s = scl_set_tiling(L, c.first, c.second);
+    s = scl_set_tiling(L, c.first, c.second, 0);
     if (s != SCL_OK) return s;
     double ms = 0;
     s = scl_step_timed(L, 2, &ms);  // warm-up (and item upload)
@@ -880,7 +905,7 @@ scl_status scl_tune(scl_lattice L, const char* cache_path) {
     if (ms < best) { best = ms; bc = c; }
   }
   L->graph_k = saved_graph;
-  s = scl_set_tiling(L, bc.first, bc.second);
+  s = scl_set_tiling(L, bc.first, bc.second, 0);
   if (s != SCL_OK) return s;
   if (cache_path) {
     std::ofstream o(cache_path, std::ios::app);

@@ -108,6 +108,8 @@ struct WorkItem {
   int x0;
   int y0, y1;
   int z0, z1;
+  int dir;  // marching direction along y (2D): +1 from y0 upward, -1 from y1 - 1 downward
+  int pad_;
 };
 
 // Optional recording of the macroscopic fields of every site a step updates (used by the
@@ -138,7 +140,7 @@ __host__ __device__ inline int wrapi(int a, int n) {
 template <class M> __device__ inline M psi_eval(M n, int kind, M eps, M inv_eps);
 
 template <> __device__ inline float psi_eval<float>(float n, int kind, float eps, float inv_eps) {
-  if (kind == 0) return expf(-1.0f / n);
+  if (kind == 0) return expf(-__builtin_amdgcn_rcpf(n));
   if (kind == 1) return powf(n / (eps + n), inv_eps);
   return 1.0f - expf(-n);
 }
@@ -155,8 +157,69 @@ template <class M> __device__ inline M dpsi_eval(M n, M psi, int kind, M eps) {
   return M(1) - psi;
 }
 
+// ------------------------------------------------------------------ fast reciprocal
+// float: the hardware reciprocal (1 ulp); double: the correctly rounded quotient.
+template <class M> __device__ inline M rcp(M x);
+template <> __device__ inline float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ inline double rcp<double>(double x) { return 1.0 / x; }
+
 // ------------------------------------------------------------------ storage conversion
 template <class S, class M> __device__ inline M ld(const S* p) { return static_cast<M>(*p); }
 template <class S, class M> __device__ inline void st(S* p, M v) { *p = static_cast<S>(v); }
+// Output store of the step: optionally non-temporal (the written state is not read again
+// within the step, so it need not displace the halo rows other workgroups re-read).
+template <class S, class M, bool NT> __device__ inline void st_out(S* p, M v) {
+  if (NT) __builtin_nontemporal_store(static_cast<S>(v), p);
+  else *p = static_cast<S>(v);
+}
+
+// ------------------------------------------------------------------ opposite velocities
+template <int VS> __host__ __device__ constexpr int opp(int i) {
+  using V = Vel<VS>;
+  for (int j = 0; j < V::Q; ++j)
+    if (V::cx(j) == -V::cx(i) && V::cy(j) == -V::cy(i) && V::cz(j) == -V::cz(i)) return j;
+  return -1;
+}
+
+// ------------------------------------------------------------------ BGK + Guo collision
+// f*_i = f_i - omega (f_i - f_i^eq) + S_i  (eqs. lbm, omega_i) with
+//   f_i^eq = w_i n [1 + xi.u/c^2 + (xi.u)^2/(2c^4) - u.u/(2c^2)]          (eq. f_eq)
+//   S_i    = kappa w_i [xi.F/c^2 + ((xi.u)(xi.F) - c^2 u.F)/c^4]          (eq. GuoForcing, T = 2uF)
+// written as f*_i = (1 - omega) f_i + A +- B for each pair (i, opposite of i): A collects the
+// terms even in xi, B the odd ones. base = n for plain storage; for shifted storage (f holds
+// f - w rho0) base = n - rho0 = sum of the stored values, which subtracts w rho0 from f^eq.
+template <int VS, class M>
+__device__ __forceinline__ void collide(const M* f, M base, M nn, M ux, M uy, M uz, M Fx, M Fy, M Fz, M omega,
+                                        M kappa, M* fo) {
+  using V = Vel<VS>;
+  constexpr int Q = V::Q;
+  const M uu15 = M(1.5) * (ux * ux + uy * uy + uz * uz);  // u.u / (2 c^2)
+  const M uF3 = M(3) * (ux * Fx + uy * Fy + uz * Fz);     // c^2 u.F / c^4
+  const M om1 = M(1) - omega;
+  const M on = omega * nn;
+  const M obase = omega * base;
+  {
+    constexpr M w = M(V::w(0));
+    fo[0] = om1 * f[0] + (w * (obase - on * uu15) - (kappa * w) * uF3);
+  }
+  static_for<Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int ib = opp<VS>(i);
+    if constexpr (i > 0 && i < ib) {
+      constexpr M w = M(V::w(i));
+      constexpr int cx = V::cx(i), cy = V::cy(i), cz = V::cz(i);
+      M xu = M(0), xF = M(0);
+      if constexpr (cx != 0) { xu += M(cx) * ux; xF += M(cx) * Fx; }
+      if constexpr (cy != 0) { xu += M(cy) * uy; xF += M(cy) * Fy; }
+      if constexpr (cz != 0) { xu += M(cz) * uz; xF += M(cz) * Fz; }
+      const M E = M(4.5) * xu * xu - uu15;
+      const M Se = M(9) * xu * xF - uF3;
+      const M A = w * (obase + on * E) + (kappa * w) * Se;
+      const M B = (M(3) * w) * (on * xu + kappa * xF);
+      fo[i] = om1 * f[i] + (A + B);
+      fo[ib] = om1 * f[ib] + (A - B);
+    }
+  });
+}
 
 }  // namespace scl

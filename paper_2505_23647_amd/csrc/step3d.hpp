@@ -77,8 +77,6 @@ k_step3d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
   constexpr int RING = 2 * R + 2;
   constexpr int NSLOT = R + 1;
   constexpr int NT = TX * TY;
-  constexpr M inv_cs2 = M(3);
-  constexpr M half_inv_cs4 = M(4.5);
 
   __shared__ M psis[RING][NT];
 
@@ -139,17 +137,21 @@ k_step3d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
 #pragma unroll
           for (int o = 0; o <= 2 * R; ++o) so[o] = (k - 2 * R + o) % RING;
           const M psic = psis[so[R]][lane];
-          M ax = M(0), ay = M(0), az = M(0);
+          M dxs[SH::NS], dys[SH::NS], dzs[SH::NS];
+#pragma unroll
+          for (int s = 0; s < SH::NS; ++s) { dxs[s] = M(0); dys[s] = M(0); dzs[s] = M(0); }
 #pragma unroll
           for (int h = 0; h < SH::NH; ++h) {
             const HalfVec hv = SH::h(h);
             const int dl = hv.y * TX + hv.x;
             const M d = psis[so[R + hv.z]][lane + dl] - psis[so[R - hv.z]][lane - dl];
-            const M wd = Wv[hv.slot] * d;
-            if (hv.x != 0) ax += M(hv.x) * wd;
-            if (hv.y != 0) ay += M(hv.y) * wd;
-            if (hv.z != 0) az += M(hv.z) * wd;
+            if (hv.x != 0) dxs[hv.slot] += M(hv.x) * d;
+            if (hv.y != 0) dys[hv.slot] += M(hv.y) * d;
+            if (hv.z != 0) dzs[hv.slot] += M(hv.z) * d;
           }
+          M ax = M(0), ay = M(0), az = M(0);
+#pragma unroll
+          for (int s = 0; s < SH::NS; ++s) { ax += Wv[s] * dxs[s]; ay += Wv[s] * dys[s]; az += Wv[s] * dzs[s]; }
           const M Fx = gpre * psic * ax, Fy = gpre * psic * ay, Fz = gpre * psic * az;
 
           M sum = M(0), jx = M(0), jy = M(0), jz = M(0);
@@ -162,25 +164,15 @@ k_step3d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
             if (V::cz(i) != 0) jz += M(V::cz(i)) * f;
           }
           const M nn = SHIFT ? rho0 + sum : sum;
-          const M inv_n = M(1) / nn;
+          const M inv_n = rcp<M>(nn);
           const M ux = (jx + M(0.5) * Fx) * inv_n;
           const M uy = (jy + M(0.5) * Fy) * inv_n;
           const M uz = (jz + M(0.5) * Fz) * inv_n;
-          const M uu15 = M(1.5) * (ux * ux + uy * uy + uz * uz);
-          const M uF3 = M(3) * (ux * Fx + uy * Fy + uz * Fz);
           const long long o = (long long)wrapi(c, nz) * plane + (long long)yw * nx + xw;
+          M fo[Q];
+          collide<1, M>(fr[js], SHIFT ? sum : nn, nn, ux, uy, uz, Fx, Fy, Fz, omega, kappa, fo);
 #pragma unroll
-          for (int i = 0; i < Q; ++i) {
-            const int cx = V::cx(i), cy = V::cy(i), cz = V::cz(i);
-            const M w = M(V::w(i));
-            const M xu = M(cx) * ux + M(cy) * uy + M(cz) * uz;
-            const M xF = M(cx) * Fx + M(cy) * Fy + M(cz) * Fz;
-            const M poly = inv_cs2 * xu + half_inv_cs4 * xu * xu - uu15;
-            const M feq = SHIFT ? w * (sum + nn * poly) : w * nn * (M(1) + poly);
-            const M src = kappa * w * (inv_cs2 * xF + M(9) * xu * xF - uF3);
-            const M f = fr[js][i];
-            st<S, M>(ob + (long long)i * cells + o, f - omega * (f - feq) + src);
-          }
+          for (int i = 0; i < Q; ++i) st<S, M>(ob + (long long)i * cells + o, fo[i]);
         }
       }
     });

@@ -113,14 +113,15 @@ class Lattice:
         check(lib().scl_get_step_count(self.h, ctypes.byref(v)))
         return v.value
 
-    def set_tiling(self, strip=0, seg=0):
-        check(lib().scl_set_tiling(self.h, int(strip), int(seg)))
+    def set_tiling(self, strip=0, seg=0, cpl=0):
+        check(lib().scl_set_tiling(self.h, int(strip), int(seg), int(cpl)))
         return self
 
     def get_tiling(self):
-        a, b = ctypes.c_int32(), ctypes.c_int32()
-        check(lib().scl_get_tiling(self.h, ctypes.byref(a), ctypes.byref(b)))
-        return a.value, b.value
+        """(strip, seg, sites per lane)."""
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().scl_get_tiling(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
 
     def tune(self, cache_path=None):
         check(lib().scl_tune(self.h, cache_path.encode() if cache_path else None))

@@ -52,31 +52,52 @@ def test_c1_droplet_fp64_parity():
     assert abs(mass[0] / ora.f.sum() - 1) < 1e-13
 
 
-@pytest.mark.parametrize("strip,seg", [(64, 7), (128, 32), (256, 0)])
-def test_extended_stencil_ragged_fp64(strip, seg):
+@pytest.mark.parametrize("strip,seg,cpl", [(64, 7, 1), (128, 32, 1), (256, 0, 1), (64, 7, 2), (128, 5, 2)])
+def test_extended_stencil_ragged_fp64(strip, seg, cpl):
     """24-vector stencil (seeded family weights), ragged sizes spanning several strips and
-    row segments, spinodal start U(0.5, 1.5), FP64, 150 steps."""
-    say(f"case: ragged 250x190 24-vector fp64 strip={strip} seg={seg}")
+    row segments (both marching directions), spinodal start U(0.5, 1.5), FP64, 150 steps;
+    one and two sites per lane."""
+    say(f"case: ragged 250x190 24-vector fp64 strip={strip} seg={seg} cpl={cpl}")
     G = coupling(0.2)
     W = family2d_weights(0.55, 0.55 ** 2 * (16 / 105) / (4 / 7) ** 2)
     dims = (250, 190)
     n0 = synth.uniform(dims, 0.9, 1.1, seed=1)
-    lat = gpu_run([dims], SCL_FP64, 1.0, G, E8_2D[0], W, n0, 150, tiling=(strip, seg))
+    lat = gpu_run([dims], SCL_FP64, 1.0, G, E8_2D[0], W, n0, 150, tiling=(strip, seg, cpl))
     ora, _ = oracle_run(dims, 1.0, G, E8_2D[0], W, n0, 150)
     assert compare_domain(lat, 0, ora, FP64_TOL) <= FP64_TOL
 
 
-@pytest.mark.parametrize("dims", [(5, 7), (3, 3), (96, 1), (1, 40), (300, 2)])
+@pytest.mark.parametrize("dims", [(5, 7), (3, 3), (96, 1), (1, 40), (300, 2), (2, 9), (4, 4), (130, 3)])
 def test_small_and_degenerate_domains_fp64(dims):
     """Domains narrower than a strip or than the stencil (periodic images), single rows and
-    columns."""
+    columns; even widths also through the two-sites-per-lane path."""
     say(f"case: degenerate dims {dims}")
     G = coupling(0.1)
     W = family2d_weights(0.5, 0.1)
     n0 = synth.uniform(dims, 0.95, 1.05, seed=3)
-    lat = gpu_run([dims], SCL_FP64, 0.9, G, E8_2D[0], W, n0, 40, tiling=(64, 5))
     ora, _ = oracle_run(dims, 0.9, G, E8_2D[0], W, n0, 40)
-    assert compare_domain(lat, 0, ora, FP64_TOL) <= FP64_TOL
+    for cpl in ((1, 2) if dims[0] % 2 == 0 else (1,)):
+        lat = gpu_run([dims], SCL_FP64, 0.9, G, E8_2D[0], W, n0, 40, tiling=(64, 5, cpl))
+        assert compare_domain(lat, 0, ora, FP64_TOL) <= FP64_TOL, cpl
+
+
+def test_two_sites_per_lane_bitwise_fp32():
+    """The vector path (two sites per lane) performs the same arithmetic per site as the
+    scalar path: bitwise equal FP32 states, over tilings with partial strips and both
+    marching directions."""
+    say("case: cpl 1 vs 2 bitwise")
+    G = coupling(0.2)
+    dims = [(1000, 330), (64, 18), (2, 7)]
+    W = family2d_weights(0.6, 0.2)
+    n0 = np.concatenate([synth.uniform(d, 0.6, 1.4, seed=20 + k) for k, d in enumerate(dims)])
+    ref = gpu_run(dims, SCL_FP32_SHIFTED, 0.9, G, E8_2D[0], W, n0, 60, tiling=(64, 9, 1))
+    pref = ref.populations()
+    for strip, seg in ((64, 9), (128, 16), (256, 31)):
+        lat = gpu_run(dims, SCL_FP32_SHIFTED, 0.9, G, E8_2D[0], W, n0, 60, tiling=(strip, seg, 2))
+        assert lat.get_tiling()[2] == 2
+        assert np.array_equal(lat.populations(), pref), (strip, seg)
+    with pytest.raises(SclError):
+        Lattice([(5, 4)], SCL_FP32).set_tiling(64, 8, 2)
 
 
 @pytest.mark.parametrize("kind,param", [(1, 14 / 29), (2, None)])
