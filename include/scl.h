@@ -182,6 +182,38 @@ scl_status scl_tune(scl_lattice lat, const char* cache_path);
  * physics, stencil or state. */
 scl_status scl_set_graph_steps(scl_lattice lat, int32_t k);
 
+/* ---------------------------------------------------------------------------------------
+ * Adjoint (reverse-mode gradients of a loss of the final state with respect to the shell
+ * weights W and the coupling G). The transpose of the step is derived from eqs. (lbm),
+ * (omega_i), (f_eq), (GuoForcing) and (sc_f); D2Q9 with FP64 or FP32 populations.
+ * ------------------------------------------------------------------------------------- */
+
+/* Advance nsteps >= 1 steps like scl_step, storing the state every `every` steps (and the
+ * initial and final states) in a device checkpoint pool owned by the lattice. Required before
+ * scl_adjoint; any later change of the state (step, init, set_populations) invalidates it. */
+scl_status scl_checkpointed_forward(scl_lattice lat, int64_t nsteps, int32_t every);
+
+/* Gradient of L through the last checkpointed forward. The seed is dL/df at the final time:
+ * seed_n (cells doubles, device) gives dL/df_i(x) = seed_n(x) for every i (a loss of the
+ * density), seed_f (Q x cells doubles, device, population layout) adds a general seed; either
+ * may be NULL. Segment by segment (last to first) the forward is recomputed from its
+ * checkpoint, recording n, j, F per step, and the adjoint step runs backwards.
+ * grad_W (ndom x nshells, host, shells in the order of scl_set_stencil) and grad_G (ndom,
+ * host) receive dL/dW and dL/dG through the time loop (the explicit dependence of a readout
+ * on W and G is added by scl_droplet_observables_vjp). Restores the final state. */
+scl_status scl_adjoint(scl_lattice lat, const double* seed_n, const double* seed_f, double* grad_W, double* grad_G);
+
+/* dL/df at the initial time of the last scl_adjoint, as doubles in the population layout. */
+scl_status scl_get_adjoint_populations(scl_lattice lat, double* out, int32_t is_device_ptr);
+
+/* Vector-Jacobian product of scl_droplet_observables at the current state: given
+ * g_obs = dL/d(observables) (ndom x 6, host) writes seed_n = dL/dn(x) (cells doubles, host or
+ * device), and the explicit derivatives of the readout: grad_W (ndom x nshells, host) and
+ * grad_G (ndom, host), which the caller adds to the scl_adjoint result. */
+scl_status scl_droplet_observables_vjp(scl_lattice lat, const int32_t* center, const int8_t* is_bubble,
+                                       const double* g_obs, double* seed_n, int32_t is_device_ptr,
+                                       double* grad_W, double* grad_G);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,10 @@ SIGNATURES = {
     "scl_get_tiling": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "scl_tune": (_I32, [_P, ctypes.c_char_p]),
     "scl_set_graph_steps": (_I32, [_P, _I32]),
+    "scl_checkpointed_forward": (_I32, [_P, _I64, _I32]),
+    "scl_adjoint": (_I32, [_P, _P, _P, _P, _P]),
+    "scl_get_adjoint_populations": (_I32, [_P, _P, _I32]),
+    "scl_droplet_observables_vjp": (_I32, [_P, _P, _P, _P, _P, _I32, _P, _P]),
 }
 
 

@@ -1,0 +1,60 @@
+"""Differentiable droplet observables: torch.autograd.Function over the library's adjoint.
+
+forward(W, G): runs the checkpointed forward on the GPU and returns the droplet observables
+(dP, C_d, R_s, sigma_s, R_e, R_e - R_s) of every domain. backward: the observables' vector-
+Jacobian product (explicit dependence on W and G plus dL/dn of the final state), then the
+adjoint through the time loop. All the arithmetic runs in libscl; this file only marshals.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .lattice import Lattice
+
+
+class DropletProblem:
+    """A batch of droplet (or bubble) domains run for a fixed number of steps.
+
+    dims: list of square (L, L); n0: concatenated initial densities; centers: (ndom, 2);
+    codes: shell codes; tau: per-domain relaxation times; psi_kind / psi_param as in scl.h.
+    """
+
+    def __init__(self, dims, n0, centers, codes, tau, nsteps, every, precision, is_bubble=None,
+                 psi_kind=0, psi_param=None, stream=None):
+        self.lat = Lattice(dims, precision, stream=stream)
+        self.n0 = np.ascontiguousarray(n0, dtype=np.float64)
+        self.centers = np.asarray(centers, dtype=np.int32)
+        self.codes = list(codes)
+        self.tau = np.broadcast_to(np.asarray(tau, dtype=np.float64), (self.lat.ndom,)).copy()
+        self.nsteps, self.every = int(nsteps), int(every)
+        self.is_bubble = is_bubble
+        self.psi_kind, self.psi_param = psi_kind, psi_param
+
+    def run(self, W, G):
+        lat = self.lat
+        lat.set_physics(self.tau, G, self.psi_kind, self.psi_param)
+        lat.set_stencil(self.codes, W)
+        lat.init_density(self.n0)
+        lat.checkpointed_forward(self.nsteps, self.every)
+        return lat.droplet_observables(self.centers, self.is_bubble)
+
+    def vjp(self, g_obs):
+        seed, gW_direct, gG_direct = self.lat.droplet_observables_vjp(self.centers, g_obs, self.is_bubble)
+        gW, gG = self.lat.adjoint(seed_n=seed)
+        return gW + gW_direct, gG + gG_direct
+
+
+class DropletObservables(torch.autograd.Function):
+    """obs = DropletObservables.apply(W, G, problem); W: (ndom, nshells), G: (ndom,) float64."""
+
+    @staticmethod
+    def forward(ctx, W, G, problem):
+        ctx.problem = problem
+        obs = problem.run(W.detach().cpu().numpy(), G.detach().cpu().numpy())
+        return torch.as_tensor(obs, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, g_obs):
+        gW, gG = ctx.problem.vjp(g_obs.detach().cpu().numpy())
+        return torch.as_tensor(gW, dtype=torch.float64), torch.as_tensor(gG, dtype=torch.float64), None

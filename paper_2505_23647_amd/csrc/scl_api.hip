@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <tuple>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -415,6 +416,71 @@ scl_status copy_out(scl_lattice_s* L, double* out, const double* src, size_t cou
   return SCL_OK;
 }
 
+// ------------------------------------------------------------------ adjoint helpers
+size_t state_bytes(const scl_lattice_s* L) { return (size_t)L->Q * L->cells * storage_bytes(L->prec); }
+
+// Work items of the adjoint kernel: 128-lane strips, 32-row ranges, same order and
+// alternating directions as the forward items.
+std::vector<WorkItem> adjoint_items(const scl_lattice_s* L, int NO, int seg) {
+  std::vector<WorkItem> items;
+  const int BAND = 8;
+  for (int k = 0; k < L->ndom; ++k) {
+    const int ns = (L->nx[k] + NO - 1) / NO;
+    const int nseg = (L->ny[k] + seg - 1) / seg;
+    for (int b0 = 0; b0 < nseg; b0 += BAND)
+      for (int sx = 0; sx < ns; ++sx)
+        for (int sg = b0; sg < std::min(b0 + BAND, nseg); ++sg) {
+          WorkItem w{};
+          w.dom = k; w.x0 = sx * NO; w.y0 = sg * seg; w.y1 = std::min((sg + 1) * seg, L->ny[k]);
+          w.z0 = 0; w.z1 = 1; w.dir = (sg % 2 == 0) ? 1 : -1;
+          items.push_back(w);
+        }
+  }
+  return items;
+}
+
+// Pair terms of the d = 2 lattice pressure tensor (same construction as k_ptensor2d):
+// P^{mu nu}(x) = n c^2 delta + G c^2 sum_t coef W[slot] psi(x + a) psi(x + b) e^mu e^nu.
+struct PTerm { double coef; int ax, ay, bx, by, ex, ey, slot; };
+
+std::vector<PTerm> ptensor_terms(const scl_lattice_s* L) {
+  std::vector<PTerm> t;
+  VecTable tab = full_table(L);
+  int slot5 = -1;
+  for (int q = 0; q < SET2N[L->set]; ++q)
+    if (SET2[L->set][q] == 5) slot5 = q;
+  for (int k = 0; k < tab.n; ++k) {
+    const int ex = tab.v[k].x, ey = tab.v[k].y, sl = tab.v[k].slot;
+    const int ax = std::abs(ex), ay = std::abs(ey);
+    if (ax * ax + ay * ay == 5) {
+      t.push_back({0.25, 0, 0, ex, ey, ex, ey, sl});
+    } else {
+      const int kk = std::max(ax, ay), hx = ex / kk, hy = ey / kk;
+      for (int m = 0; m < kk; ++m) t.push_back({1.0 / (2.0 * kk), -m * hx, -m * hy, -m * hx + ex, -m * hy + ey, ex, ey, sl});
+    }
+  }
+  if (slot5 >= 0) {
+    const int ev[4][2] = {{2, 1}, {1, 2}, {-1, 2}, {-2, 1}};
+    const int pr[4][2][4] = {{{-1, 0, 1, 1}, {-1, -1, 1, 0}}, {{-1, -1, 0, 1}, {0, -1, 1, 1}},
+                             {{0, -1, -1, 1}, {1, -1, 0, 1}}, {{1, -1, -1, 0}, {1, 0, -1, 1}}};
+    for (int v = 0; v < 4; ++v)
+      for (int p = 0; p < 2; ++p)
+        t.push_back({0.25, pr[v][p][0], pr[v][p][1], pr[v][p][2], pr[v][p][3], ev[v][0], ev[v][1], slot5});
+  }
+  return t;
+}
+
+double psi_host(double n, int kind, double eps) {
+  if (kind == 0) return std::exp(-1.0 / n);
+  if (kind == 1) return std::pow(n / (eps + n), 1.0 / eps);
+  return 1.0 - std::exp(-n);
+}
+double dpsi_host(double n, double psi, int kind, double eps) {
+  if (kind == 0) return psi / (n * n);
+  if (kind == 1) return psi / (n * (eps + n));
+  return 1.0 - psi;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -596,6 +662,7 @@ scl_status scl_init_density(scl_lattice L, const double* n0, int32_t is_dev) {
   HIPCHK(hipFree(dn));
   L->have_state = true;
   L->steps = 0;
+  L->adj.valid = false;
   drop_graph(L);
   return SCL_OK;
 }
@@ -710,6 +777,7 @@ scl_status scl_set_populations(scl_lattice L, const double* in, int32_t is_dev) 
   }
   HIPCHK(hipStreamSynchronize(L->stream));
   if (tmp) HIPCHK(hipFree(tmp));
+  L->adj.valid = false;
   drop_graph(L);
   return SCL_OK;
 }
@@ -911,6 +979,277 @@ scl_status scl_tune(scl_lattice L, const char* cache_path) {
     std::ofstream o(cache_path, std::ios::app);
     o << ks << "|" << bc.first << " " << bc.second << "\n";
   }
+  return SCL_OK;
+}
+
+scl_status scl_checkpointed_forward(scl_lattice L, int64_t nsteps, int32_t every) {
+  if (!L || nsteps < 1 || every < 1) return fail(SCL_E_INVALID, "need nsteps >= 1 and every >= 1");
+  if (L->d != 2) return fail(SCL_E_UNSUPPORTED, "the adjoint is implemented for D2Q9");
+  if (L->prec == SCL_FP16S_FP32) return fail(SCL_E_UNSUPPORTED, "the adjoint needs FP32 or FP64 populations");
+  scl_status s = ready(L);
+  if (s != SCL_OK) return s;
+  AdjointState& a = L->adj;
+  const size_t sb = state_bytes(L);
+  const int nfull = (int)(nsteps / every);
+  const int slots = nfull + 2;  // states at 0, every, ..., nfull*every, and the final one
+  if (a.pool_bytes < (size_t)slots * sb) {
+    if (a.pool) HIPCHK(hipFree(a.pool));
+    a.pool = nullptr;
+    a.pool_bytes = 0;
+    if (hipMalloc(&a.pool, (size_t)slots * sb) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SCL_E_NOMEM, "checkpoint pool does not fit in device memory");
+    }
+    a.pool_bytes = (size_t)slots * sb;
+  }
+  char* pool = (char*)a.pool;
+  HIPCHK(hipMemcpyAsync(pool, L->A, sb, hipMemcpyDeviceToDevice, L->stream));
+  int64_t done = 0;
+  for (int c = 1; c <= nfull; ++c) {
+    s = do_steps(L, every);
+    if (s != SCL_OK) return s;
+    done += every;
+    HIPCHK(hipMemcpyAsync(pool + (size_t)c * sb, L->A, sb, hipMemcpyDeviceToDevice, L->stream));
+  }
+  if (done < nsteps) {
+    s = do_steps(L, nsteps - done);
+    if (s != SCL_OK) return s;
+  }
+  HIPCHK(hipMemcpyAsync(pool + (size_t)(nfull + 1) * sb, L->A, sb, hipMemcpyDeviceToDevice, L->stream));
+  a.nckpt = slots;
+  a.every = every;
+  a.nsteps = nsteps;
+  a.valid = true;
+  a.end_step = L->steps;
+  return SCL_OK;
+}
+
+scl_status scl_adjoint(scl_lattice L, const double* seed_n, const double* seed_f, double* grad_W, double* grad_G) {
+  if (!L || !grad_W || !grad_G) return fail(SCL_E_INVALID, "gradient outputs are required");
+  AdjointState& a = L->adj;
+  if (!a.valid || a.end_step != L->steps) return fail(SCL_E_STATE, "run scl_checkpointed_forward first (and leave the state unchanged)");
+  scl_status s = sync_params(L);
+  if (s != SCL_OK) return s;
+  const bool f64 = L->prec == SCL_FP64;
+  const size_t ms = f64 ? 8 : 4;
+  const size_t sb = state_bytes(L);
+  const long long C = L->cells;
+  const int every = a.every;
+  // buffers
+  const size_t rec_need = (size_t)every * 5 * C * ms;
+  if (a.rec_bytes < rec_need) {
+    if (a.rec) HIPCHK(hipFree(a.rec));
+    a.rec = nullptr;
+    if (hipMalloc(&a.rec, rec_need) != hipSuccess) { (void)hipGetLastError(); a.rec_bytes = 0; return fail(SCL_E_NOMEM, "recompute buffer does not fit"); }
+    a.rec_bytes = rec_need;
+  }
+  const size_t lam_need = (size_t)L->Q * C * ms;
+  if (a.lam_bytes < lam_need) {
+    for (int b = 0; b < 2; ++b) {
+      if (a.lam[b]) HIPCHK(hipFree(a.lam[b]));
+      a.lam[b] = nullptr;
+      if (hipMalloc(&a.lam[b], lam_need) != hipSuccess) { (void)hipGetLastError(); a.lam_bytes = 0; return fail(SCL_E_NOMEM, "adjoint buffers do not fit"); }
+    }
+    a.lam_bytes = lam_need;
+  }
+  constexpr int NO = 128;
+  std::vector<WorkItem> items = adjoint_items(L, NO, 32);
+  WorkItem* d_items = nullptr;
+  HIPCHK(hipMalloc(&d_items, sizeof(WorkItem) * items.size()));
+  HIPCHK(hipMemcpy(d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice));
+  const int nitems = (int)items.size();
+  const int NSG = 1 + ADJ_MAXS;
+  if (a.gpart_cap < (size_t)nitems * NSG) {
+    if (a.gpart) HIPCHK(hipFree(a.gpart));
+    HIPCHK(hipMalloc(&a.gpart, sizeof(double) * nitems * NSG));
+    a.gpart_cap = (size_t)nitems * NSG;
+  }
+  // seed
+  std::vector<DomDev> doms = host_doms(L);
+  for (int k = 0; k < L->ndom; ++k) {
+    const long long c = (long long)L->nx[k] * L->ny[k];
+    if (f64) hipLaunchKernelGGL(k_adj_seed<double>, dim3(blocks_for(c, 256)), dim3(256), 0, L->stream, (double*)a.lam[0], seed_n, seed_f, doms[k], L->Q);
+    else hipLaunchKernelGGL(k_adj_seed<float>, dim3(blocks_for(c, 256)), dim3(256), 0, L->stream, (float*)a.lam[0], seed_n, seed_f, doms[k], L->Q);
+    HIPCHK(hipGetLastError());
+  }
+  int cur = 0;
+  bool first = true;
+  const int per = (nitems + 7) / 8;
+  char* pool = (char*)a.pool;
+  const int nseg = (int)((a.nsteps + every - 1) / every);
+  for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+    const long long t0 = (long long)sgi * every;
+    const long long t1 = std::min<long long>(t0 + every, a.nsteps);
+    HIPCHK(hipMemcpyAsync(L->A, pool + (size_t)sgi * sb, sb, hipMemcpyDeviceToDevice, L->stream));
+    // recompute the segment, recording n, j, F of every step
+    for (long long t = t0; t < t1; ++t) {
+      char* base = (char*)a.rec + (size_t)(t - t0) * 5 * C * ms;
+      hipError_t e;
+      if (f64) {
+        MacroRec<double> r{(double*)base, (double*)base + C, (double*)base + 3 * C, C};
+        e = launch_step(L, L->A, L->B, &r, nullptr);
+      } else {
+        MacroRec<float> r{(float*)base, (float*)base + C, (float*)base + 3 * C, C};
+        e = launch_step(L, L->A, L->B, nullptr, &r);
+      }
+      if (e != hipSuccess) { (void)hipFree(d_items); return fail(SCL_E_DEVICE, std::string("recompute: ") + hipGetErrorString(e)); }
+      std::swap(L->A, L->B);
+    }
+    // adjoint steps, last to first
+    for (long long t = t1 - 1; t >= t0; --t) {
+      char* base = (char*)a.rec + (size_t)(t - t0) * 5 * C * ms;
+      const int acc = first ? 0 : 1;
+#define ADJ_LAUNCH(M_, SETV)                                                                              \
+  hipLaunchKernelGGL((k_adjoint2d<M_, SETV, NO>), dim3(8 * per), dim3(NO + 2 * Shells<2, SETV>::R), 0, L->stream, \
+                     (const M_*)a.lam[cur], (M_*)a.lam[1 - cur], (const M_*)base, (const M_*)base + C,          \
+                     (const M_*)base + 3 * C, C, L->d_doms, d_items, nitems, a.gpart, acc)
+      if (f64) { if (L->set == 0) ADJ_LAUNCH(double, 0); else ADJ_LAUNCH(double, 1); }
+      else { if (L->set == 0) ADJ_LAUNCH(float, 0); else ADJ_LAUNCH(float, 1); }
+#undef ADJ_LAUNCH
+      HIPCHK(hipGetLastError());
+      cur = 1 - cur;
+      first = false;
+    }
+  }
+  // restore the final state
+  HIPCHK(hipMemcpyAsync(L->A, pool + (size_t)(a.nckpt - 1) * sb, sb, hipMemcpyDeviceToDevice, L->stream));
+  std::vector<double> part((size_t)nitems * NSG);
+  HIPCHK(hipMemcpyAsync(part.data(), a.gpart, part.size() * sizeof(double), hipMemcpyDeviceToHost, L->stream));
+  HIPCHK(hipStreamSynchronize(L->stream));
+  HIPCHK(hipFree(d_items));
+  a.lam_cur = cur;
+  // per-domain sums in item order; slot order -> the caller's shells
+  const int NS = SET2N[L->set];
+  const int nsh = (int)L->user_codes.size();
+  std::vector<double> gs((size_t)L->ndom * (NS + 1), 0.0);
+  for (int i = 0; i < nitems; ++i)
+    for (int q = 0; q <= NS; ++q)
+      gs[(size_t)items[i].dom * (NS + 1) + q] += part[(size_t)i * NSG + (q < NS ? q : ADJ_MAXS)];
+  for (int k = 0; k < L->ndom; ++k) {
+    for (int u = 0; u < nsh; ++u) grad_W[(size_t)k * nsh + u] = gs[(size_t)k * (NS + 1) + L->slot_of_user[u]];
+    grad_G[k] = gs[(size_t)k * (NS + 1) + NS];
+  }
+  return SCL_OK;
+}
+
+scl_status scl_get_adjoint_populations(scl_lattice L, double* out, int32_t is_dev) {
+  if (!L || !out) return fail(SCL_E_INVALID, "bad arguments");
+  AdjointState& a = L->adj;
+  if (!a.lam[a.lam_cur]) return fail(SCL_E_STATE, "no adjoint has been computed");
+  const size_t n = (size_t)L->Q * L->cells;
+  double* dst = out;
+  if (!is_dev) HIPCHK(hipMalloc(&dst, n * sizeof(double)));
+  if (L->prec == SCL_FP64) hipLaunchKernelGGL(k_adj_get<double>, dim3(blocks_for((long long)n, 256)), dim3(256), 0, L->stream, (const double*)a.lam[a.lam_cur], dst, (long long)n);
+  else hipLaunchKernelGGL(k_adj_get<float>, dim3(blocks_for((long long)n, 256)), dim3(256), 0, L->stream, (const float*)a.lam[a.lam_cur], dst, (long long)n);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(L->stream));
+  if (!is_dev) {
+    HIPCHK(hipMemcpy(out, dst, n * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipFree(dst));
+  }
+  return SCL_OK;
+}
+
+scl_status scl_droplet_observables_vjp(scl_lattice L, const int32_t* center, const int8_t* is_bubble, const double* gobs,
+                                       double* seed_n, int32_t is_dev, double* grad_W, double* grad_G) {
+  if (!L || !center || !gobs || !seed_n || !grad_W || !grad_G) return fail(SCL_E_INVALID, "bad arguments");
+  if (L->d != 2) return fail(SCL_E_UNSUPPORTED, "droplet observables are implemented for D2Q9 only");
+  for (int k = 0; k < L->ndom; ++k) {
+    if (L->nx[k] != L->ny[k]) return fail(SCL_E_INVALID, "droplet observables need square domains");
+    if (center[2 * k] < 0 || center[2 * k] >= L->nx[k] || center[2 * k + 1] < 0 || center[2 * k + 1] >= L->ny[k])
+      return fail(SCL_E_INVALID, "centre outside the domain");
+  }
+  scl_status s = compute_fields(L, false);
+  if (s != SCL_OK) return s;
+  std::vector<double> n((size_t)L->cells);
+  HIPCHK(hipMemcpyAsync(n.data(), L->d_n, n.size() * sizeof(double), hipMemcpyDeviceToHost, L->stream));
+  HIPCHK(hipStreamSynchronize(L->stream));
+  const std::vector<PTerm> terms = ptensor_terms(L);
+  const int nsh = (int)L->user_codes.size();
+  std::vector<double> gn((size_t)L->cells, 0.0);
+  for (int k = 0; k < L->ndom; ++k) {
+    const int Ls = L->nx[k], cx = center[2 * k], cy = center[2 * k + 1];
+    const long long o = L->off[k];
+    const double G = L->G[k];
+    const double Gc2 = G * CS2;
+    const double* W = &L->Wslot[(size_t)k * MAX_SHELLS];
+    auto idx = [&](int x, int y) { return (size_t)(o + (long long)wrapi(y, Ls) * Ls + wrapi(x, Ls)); };
+    auto psi = [&](int x, int y) { return psi_host(n[idx(x, y)], L->psi_kind, L->psi_param[k]); };
+    auto P = [&](int x, int y, double& xx, double& yy) {
+      double sxx = 0, syy = 0;
+      for (const PTerm& t : terms) {
+        const double v = t.coef * W[t.slot] * psi(x + t.ax, y + t.ay) * psi(x + t.bx, y + t.by);
+        sxx += v * t.ex * t.ex;
+        syy += v * t.ey * t.ey;
+      }
+      xx = n[idx(x, y)] * CS2 + Gc2 * sxx;
+      yy = n[idx(x, y)] * CS2 + Gc2 * syy;
+    };
+    // forward quantities
+    double pcx, pcy, pox, poy;
+    P(cx, cy, pcx, pcy);
+    P(0, 0, pox, poy);
+    const double Pbc = 0.5 * (pcx + pcy), Pbo = 0.5 * (pox + poy), dP = Pbc - Pbo;
+    const int Rm = Ls / 2;
+    double Cd = 0, wsum = 0;
+    for (int sg = -1; sg <= 1; sg += 2)
+      for (int r = 0; r <= Rm; ++r) {
+        double xx, yy;
+        P(cx + sg * r, cy, xx, yy);
+        const double tw = (r == 0 || r == Rm) ? 0.5 : 1.0;
+        Cd += 0.5 * tw * r * (Pbo - yy);
+        wsum += 0.5 * tw * r;
+      }
+    double M = 0;
+    for (long long c = 0; c < (long long)Ls * Ls; ++c) M += n[(size_t)(o + c)];
+    const double Rs = std::sqrt(2.0 * Cd / dP);
+    const double sgn = (is_bubble && is_bubble[k]) ? -1.0 : 1.0;
+    const double nin = n[idx(cx, cy)], nout = n[idx(0, 0)];
+    const double Nn = M - (double)Ls * Ls * nout, Dd = M_PI * (nin - nout);
+    const double Re = std::sqrt(Nn / Dd);
+    // backward through the closed forms
+    const double* g = gobs + (size_t)6 * k;
+    const double gRs = g[2] + g[3] * sgn * dP - g[5];
+    const double gRe = g[4] + g[5];
+    const double gdP = g[0] + g[3] * sgn * Rs - gRs * Rs / (2.0 * dP);
+    const double gCd = g[1] + gRs / (Rs * dP);
+    const double gN = gRe / (2.0 * Re * Dd), gD = -gRe * Nn / (2.0 * Re * Dd * Dd);
+    const double gM = gN, gno = -(double)Ls * Ls * gN - M_PI * gD, gnc = M_PI * gD;
+    // gradients on P components at sites: (site, gPxx, gPyy)
+    std::vector<std::tuple<int, int, double, double>> gp;
+    const double gPbo = -gdP + gCd * wsum;
+    gp.emplace_back(cx, cy, 0.5 * gdP, 0.5 * gdP);
+    gp.emplace_back(0, 0, 0.5 * gPbo, 0.5 * gPbo);
+    for (int sg = -1; sg <= 1; sg += 2)
+      for (int r = 1; r <= Rm; ++r) {
+        const double tw = (r == Rm) ? 0.5 : 1.0;
+        gp.emplace_back(cx + sg * r, cy, 0.0, -gCd * 0.5 * tw * r);
+      }
+    std::vector<double> gWs(MAX_SHELLS, 0.0);
+    double gG = 0.0;
+    for (const auto& e : gp) {
+      const int x = std::get<0>(e), y = std::get<1>(e);
+      const double gxx = std::get<2>(e), gyy = std::get<3>(e);
+      gn[idx(x, y)] += CS2 * (gxx + gyy);
+      for (const PTerm& t : terms) {
+        const double wgt = gxx * t.ex * t.ex + gyy * t.ey * t.ey;
+        if (wgt == 0.0) continue;
+        const double pa = psi(x + t.ax, y + t.ay), pb = psi(x + t.bx, y + t.by);
+        const double c0 = wgt * t.coef;
+        const size_t ia = idx(x + t.ax, y + t.ay), ib = idx(x + t.bx, y + t.by);
+        gn[ia] += c0 * Gc2 * W[t.slot] * pb * dpsi_host(n[ia], pa, L->psi_kind, L->psi_param[k]);
+        gn[ib] += c0 * Gc2 * W[t.slot] * pa * dpsi_host(n[ib], pb, L->psi_kind, L->psi_param[k]);
+        gWs[t.slot] += c0 * Gc2 * pa * pb;
+        gG += c0 * CS2 * W[t.slot] * pa * pb;
+      }
+    }
+    for (long long c = 0; c < (long long)Ls * Ls; ++c) gn[(size_t)(o + c)] += gM;
+    gn[idx(cx, cy)] += gnc;
+    gn[idx(0, 0)] += gno;
+    for (int u = 0; u < nsh; ++u) grad_W[(size_t)k * nsh + u] = gWs[L->slot_of_user[u]];
+    grad_G[k] = gG;
+  }
+  HIPCHK(hipMemcpy(seed_n, gn.data(), gn.size() * sizeof(double), is_dev ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
   return SCL_OK;
 }
 

@@ -86,6 +86,7 @@ class Lattice:
             W = np.tile(W, (self.ndom, 1))
         W = np.ascontiguousarray(W)
         check(lib().scl_set_stencil(self.h, len(codes), _dptr(codes), _dptr(W)))
+        self._nshells = len(codes)
         return self
 
     def init_density(self, n0):
@@ -177,3 +178,48 @@ class Lattice:
         out = np.empty((self.ndom, 6))
         check(lib().scl_droplet_observables(self.h, _dptr(c), _dptr(b) if b is not None else None, _dptr(out)))
         return out
+
+    # ------------------------------------------------------------------ adjoint
+    def checkpointed_forward(self, nsteps, every):
+        check(lib().scl_checkpointed_forward(self.h, int(nsteps), int(every)))
+        return self
+
+    def adjoint(self, seed_n=None, seed_f=None):
+        """Gradients (dL/dW [ndom, nshells], dL/dG [ndom]) through the last checkpointed forward.
+
+        seed_n / seed_f: dL/dn(x) (cells) and dL/df (populations) at the final time, as torch
+        tensors on the GPU or numpy arrays (copied to the GPU).
+        """
+        import torch
+
+        def dev(a):
+            if a is None:
+                return None
+            if _is_torch_cuda(a):
+                return a.to(torch.float64).contiguous()
+            return torch.as_tensor(np.asarray(a, dtype=np.float64)).cuda().contiguous()
+
+        sn, sf = dev(seed_n), dev(seed_f)
+        nsh = self._nshells
+        gW = np.zeros((self.ndom, nsh))
+        gG = np.zeros(self.ndom)
+        check(lib().scl_adjoint(self.h, ctypes.c_void_p(sn.data_ptr()) if sn is not None else None,
+                                ctypes.c_void_p(sf.data_ptr()) if sf is not None else None, _dptr(gW), _dptr(gG)))
+        return gW, gG
+
+    def adjoint_populations(self):
+        return self._get(lib().scl_get_adjoint_populations, self.Q * self.cells)
+
+    def droplet_observables_vjp(self, centers, g_obs, is_bubble=None):
+        """(seed_n [cells] host array, direct dL/dW [ndom, nshells], direct dL/dG [ndom])."""
+        c = np.ascontiguousarray(np.asarray(centers, dtype=np.int32).reshape(self.ndom, 2))
+        b = None
+        if is_bubble is not None:
+            b = np.ascontiguousarray(np.asarray(is_bubble, dtype=np.int8).reshape(self.ndom))
+        g = np.ascontiguousarray(np.asarray(g_obs, dtype=np.float64).reshape(self.ndom, 6))
+        seed = np.zeros(self.cells)
+        gW = np.zeros((self.ndom, self._nshells))
+        gG = np.zeros(self.ndom)
+        check(lib().scl_droplet_observables_vjp(self.h, _dptr(c), _dptr(b) if b is not None else None, _dptr(g),
+                                                _dptr(seed), 0, _dptr(gW), _dptr(gG)))
+        return seed, gW, gG

@@ -1,0 +1,188 @@
+"""The hand-written adjoint (checkpointed recompute + reverse step kernel) on the GPU.
+
+Checks: the gradient of droplet observables against the FP64 oracle's tangent-linear
+(dual-number) Jacobian; a dot-product test of one reverse step; central finite differences
+(Richardson-extrapolated) of the whole pipeline; FP32 against FP64; the autograd wrapper.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import thermo
+from paper_2505_23647_amd import SCL_FP32, SCL_FP64, Lattice, synth
+from paper_2505_23647_amd.autograd import DropletObservables, DropletProblem
+from tests.gpu_helpers import E8_2D, coupling, family2d_weights, perm_to_oracle, say
+
+pytestmark = pytest.mark.gpu
+
+CODES = E8_2D[0]
+
+
+def droplet_batch(sides, radii, seed0=0):
+    G = coupling(0.2)
+    ng, nl, _ = thermo.coexistence(G)
+    n0s = [synth.droplet((L, L), R, nl, ng, noise=1e-3, seed=seed0 + k) for k, (L, R) in enumerate(zip(sides, radii))]
+    centers = [(L // 2, L // 2) for L in sides]
+    return G, n0s, centers
+
+
+def test_gradient_matches_oracle_tangent_linear():
+    """FP64: d(loss)/d(W, G) from the GPU adjoint equals the oracle's forward-mode Jacobian
+    contracted with the same dL/dobs (loss weights on sigma_s and delta), per domain."""
+    say("case: adjoint vs oracle tangent-linear")
+    # sizes and step counts where the droplets have stopped ringing (Delta P > 0, C_d > 0)
+    sides, radii = [36, 40], [9.0, 10.0]
+    G, n0s, centers = droplet_batch(sides, radii)
+    Ws = [family2d_weights(0.6, 0.15), family2d_weights(0.62, 0.16)]
+    steps, every = 800, 45
+    gobs_all, ref_grads = [], []
+    for k, L in enumerate(sides):
+        obs, jac = oracle.droplet_tangent_linear((L, L), 1.0, G, CODES, Ws[k], n0s[k], steps, centers[k])
+        assert np.all(np.isfinite(obs)) and obs[0] > 0 and obs[1] > 0
+        gobs = np.zeros(6)
+        gobs[3] = 2 * (obs[3] - 1.05 * obs[3])
+        gobs[5] = 2 * (obs[5] - (obs[5] + 0.5))
+        gobs_all.append(gobs)
+        ref_grads.append(gobs @ jac)
+    prob = DropletProblem([(L, L) for L in sides], np.concatenate(n0s), centers, CODES, 1.0, steps, every, SCL_FP64)
+    obs_gpu = prob.run(np.array(Ws), np.full(2, G))
+    for k, L in enumerate(sides):
+        o_ref, _ = oracle.droplet_tangent_linear((L, L), 1.0, G, CODES, Ws[k], n0s[k], steps, centers[k])
+        assert np.allclose(obs_gpu[k], o_ref, rtol=1e-10, atol=1e-12), k
+    gW, gG = prob.vjp(np.array(gobs_all))
+    for k in range(2):
+        got = np.concatenate([gW[k], [gG[k]]])
+        ref = ref_grads[k]
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        say(f"  domain {k}: rel err vs tangent-linear {err:.2e}")
+        assert err < 1e-8, (k, got, ref)
+
+
+def test_reverse_step_dot_product():
+    """<J v, w> = <v, J^T w> for one step (FP64), with J v from central differences."""
+    say("case: adjoint dot-product test")
+    G = coupling(0.2)
+    dims = (40, 30)
+    W = family2d_weights(0.55, 0.12)
+    n0 = synth.uniform(dims, 0.7, 1.3, seed=11)
+    lat = Lattice([dims], SCL_FP64).set_physics(0.9, G).set_stencil(CODES, W).init_density(n0)
+    lat.step(20)
+    f = lat.populations()
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(f.size)
+    w = rng.standard_normal(f.size)
+    lat.set_populations(f)
+    lat.checkpointed_forward(1, 1)
+    lat.adjoint(seed_f=w)
+    lam0 = lat.adjoint_populations()
+    h = 1e-6
+    outs = []
+    for sgn in (1, -1):
+        lat.set_populations(f + sgn * h * v)
+        lat.step(1)
+        outs.append(lat.populations())
+    jv = (outs[0] - outs[1]) / (2 * h)
+    lhs, rhs = float(jv @ w), float(v @ lam0)
+    say(f"  <Jv,w> = {lhs:.12e}  <v,J^T w> = {rhs:.12e}")
+    assert abs(lhs - rhs) <= 1e-7 * abs(rhs)
+
+
+def _loss_problem(prec, steps=800, every=45):
+    sides, radii = [48, 40], [12.0, 10.0]
+    G, n0s, centers = droplet_batch(sides, radii, seed0=30)
+    W = np.array([family2d_weights(0.55, 0.12), family2d_weights(0.62, 0.16)])
+    prob = DropletProblem([(L, L) for L in sides], np.concatenate(n0s), centers, CODES, 1.0, steps, every, prec)
+    return prob, W, np.full(2, G)
+
+
+def _loss(obs, tgt):
+    return ((obs[:, 3] - tgt[:, 0]) ** 2 + (obs[:, 5] - tgt[:, 1]) ** 2)
+
+
+def test_gradient_matches_finite_differences_fp64():
+    """Central differences of the full pipeline (forward, readout, loss), Richardson
+    extrapolated from steps h and h/2, against the adjoint: 1e-6 relative per domain."""
+    say("case: adjoint vs finite differences fp64")
+    prob, W, G = _loss_problem(SCL_FP64)
+    obs = prob.run(W, G)
+    assert np.all(np.isfinite(obs)) and np.all(obs[:, 0] > 0) and np.all(obs[:, 1] > 0)
+    tgt = np.stack([obs[:, 3] * 1.05, obs[:, 5] + 0.5], axis=1)
+    gobs = np.zeros_like(obs)
+    gobs[:, 3] = 2 * (obs[:, 3] - tgt[:, 0])
+    gobs[:, 5] = 2 * (obs[:, 5] - tgt[:, 1])
+    gW, gG = prob.vjp(gobs)
+    grad = np.concatenate([gW, gG[:, None]], axis=1)
+
+    def per_domain_loss(Wp, Gp):
+        return _loss(prob.run(Wp, Gp), tgt)
+
+    fd = np.zeros_like(grad)
+    for q in range(grad.shape[1]):
+        base = np.abs(W[:, q]) if q < W.shape[1] else np.abs(G)
+        h = 1e-4 * np.maximum(base, 1e-2)
+        D = []
+        for hh in (h, h / 2):
+            vals = []
+            for sgn in (1, -1):
+                Wp, Gp = W.copy(), G.copy()
+                if q < W.shape[1]:
+                    Wp[:, q] += sgn * hh
+                else:
+                    Gp += sgn * hh
+                vals.append(per_domain_loss(Wp, Gp))
+            D.append((vals[0] - vals[1]) / (2 * hh))
+        fd[:, q] = (4 * D[1] - D[0]) / 3
+    for k in range(grad.shape[0]):
+        err = np.abs(grad[k] - fd[k]).max() / np.abs(fd[k]).max()
+        say(f"  domain {k}: rel err vs FD {err:.2e}")
+        assert err < 1e-6, (k, grad[k], fd[k])
+
+
+def test_fp32_gradient_close_to_fp64():
+    """FP32 populations: the adjoint gradient within 2e-3 (relative to the largest component)
+    of the FP64 one on the same problem (measured values printed)."""
+    say("case: adjoint fp32 vs fp64")
+    grads = []
+    for prec in (SCL_FP64, SCL_FP32):
+        prob, W, G = _loss_problem(prec)
+        obs = prob.run(W, G)
+        gobs = np.zeros_like(obs)
+        gobs[:, 3] = 1.0
+        gobs[:, 5] = 1.0
+        gW, gG = prob.vjp(gobs)
+        grads.append(np.concatenate([gW, gG[:, None]], axis=1))
+    for k in range(2):
+        err = np.abs(grads[1][k] - grads[0][k]).max() / np.abs(grads[0][k]).max()
+        say(f"  domain {k}: fp32 vs fp64 rel err {err:.2e}")
+        assert err < 2e-3
+
+
+def test_autograd_function():
+    """torch.autograd through DropletObservables gives the library's gradient."""
+    say("case: autograd wrapper")
+    prob, W0, G0 = _loss_problem(SCL_FP64, steps=800, every=30)
+    W = torch.tensor(W0, requires_grad=True)
+    G = torch.tensor(G0, requires_grad=True)
+    obs = DropletObservables.apply(W, G, prob)
+    loss = (obs[:, 3] ** 2).sum() + (obs[:, 5] ** 2).sum()
+    loss.backward()
+    gobs = np.zeros((2, 6))
+    o = obs.detach().numpy()
+    gobs[:, 3] = 2 * o[:, 3]
+    gobs[:, 5] = 2 * o[:, 5]
+    prob.run(W0, G0)
+    gW, gG = prob.vjp(gobs)
+    assert np.allclose(W.grad.numpy(), gW, rtol=1e-12, atol=0)
+    assert np.allclose(G.grad.numpy(), gG, rtol=1e-12, atol=0)
+
+
+def test_adjoint_requires_checkpointed_forward():
+    from paper_2505_23647_amd import SclError
+    lat = Lattice([(16, 16)], SCL_FP64).set_physics(1.0, -6.0).set_stencil(*E8_2D).init_density(np.ones(256))
+    with pytest.raises(SclError):
+        lat.adjoint(seed_n=np.ones(256))
+    lat.checkpointed_forward(5, 2)
+    lat.step(1)  # changes the state: the checkpoints no longer describe it
+    with pytest.raises(SclError):
+        lat.adjoint(seed_n=np.ones(256))
