@@ -62,6 +62,82 @@ def timed(lat, steps, warmup):
     return ms
 
 
+def c5_problem(prec, stream=None):
+    """Batched droplet workload of the adjoint: 16 D2Q9 domains of 256 x 256, each with its own
+    seeded shell weights (shells {1,2,4,5,8}), a droplet of radius 40 at the flat coexistence
+    densities relaxed for 20000 steps, then a differentiated window of 2000 steps with
+    checkpoints every 45 steps."""
+    from paper_2505_23647_amd import stencil, synth, thermo
+    from paper_2505_23647_amd.autograd import DropletProblem
+    L, R, ndom, steps, every = 256, 40.0, 16, 2000, 45
+    G = thermo.coupling_for_reduced_temperature(0.2)
+    ng, nl, _ = thermo.coexistence_exp(G)
+    W = np.array([stencil.seeded_family2d(*synth.knob_draws(5 + b, 2, 0.0, 1.0))[2] for b in range(ndom)])
+    n0 = np.concatenate([synth.droplet((L, L), R, nl, ng, noise=1e-3, seed=100 + b) for b in range(ndom)])
+    prob = DropletProblem([(L, L)] * ndom, n0, [(L // 2, L // 2)] * ndom, [1, 2, 4, 5, 8], 1.0, steps, every,
+                          prec, stream=stream, equilibrate=20000)
+    return prob, W, np.full(ndom, G)
+
+
+def c5_targets(obs):
+    """Seeded targets: sigma* = sigma (1 + 0.05 u), delta* = delta + 0.5 u', u, u' ~ U(-1, 1)."""
+    from paper_2505_23647_amd import synth
+    ndom = obs.shape[0]
+    u = synth.knob_draws(7, 2 * ndom, -1.0, 1.0)
+    return obs[:, 3] * (1 + 0.05 * u[:ndom]), obs[:, 5] + 0.5 * u[ndom:]
+
+
+def adjoint_leg(stream):
+    """Wall time of the checkpointed forward (with the observables) and of the backward
+    (observables VJP + recompute + reverse steps) on the batched droplet workload, FP32;
+    loss = squared error of sigma_s and delta against seeded targets."""
+    import torch
+    from paper_2505_23647_amd import SCL_FP32_SHIFTED
+    prob, W, G = c5_problem(SCL_FP32_SHIFTED, stream)
+    prob.run(W, G)  # relaxation, allocations, code objects
+    prob.load(W, G)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    obs = prob.forward()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ts, td = c5_targets(obs)
+    g = np.zeros_like(obs)
+    g[:, 3] = 2 * (obs[:, 3] - ts)
+    g[:, 5] = 2 * (obs[:, 5] - td)
+    t2 = time.perf_counter()
+    gW, gG = prob.vjp(g)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    fwd, bwd = t1 - t0, t3 - t2
+    prob.lat.close()
+    return {"workload": "16 x D2Q9 256^2 droplets R=40 (relaxed 20000 steps), 2000-step window FP32 shifted storage, checkpoints every 45",
+            "forward_s": round(fwd, 4), "backward_s": round(bwd, 4), "ratio": round(bwd / fwd, 3),
+            "grad_finite": bool(np.all(np.isfinite(gW)) and np.all(np.isfinite(gG)))}
+
+
+def d3q19_leg(stream, steps=40):
+    """D3Q19 512^3 FP32 with the 92-vector stencil (seeded weights near 3D E(8)), tau = 0.8,
+    n0 = 1 + U(-1e-2, 1e-2): MLUPS and algorithmic HBM bandwidth (2 x 19 x 4 bytes/site)."""
+    from paper_2505_23647_amd import SCL_FP32, Lattice, stencil, synth
+    dims = (512, 512, 512)
+    u = synth.knob_draws(3, 3, 0.0, 1.0)
+    W = stencil.seeded_family3d(*u)[3]
+    G = -1.2 * np.e ** 2
+    n0 = synth.around(dims, 1.0, 1e-2, seed=4)
+    lat = Lattice([dims], SCL_FP32, stream=stream).set_physics(0.8, G).set_stencil(list(stencil.SHELLS_3D), W)
+    lat.init_density(n0)
+    del n0
+    lat.step(5)
+    ms = lat.step_timed(steps)
+    cells = 512 ** 3
+    ml = cells * steps / (ms / 1e3) / 1e6
+    ach = 2 * 19 * 4 * cells / (ms / 1e3 / steps) / 1e9
+    lat.close()
+    return {"MLUPS": round(ml, 1), "achieved_GBs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+            "steps": steps, "stencil_vectors": 92}
+
+
 def cpu_baseline(W, G, n0_full, budget_s=12.0):
     """The FP64 oracle on the host cores, on a 1024 x 1024 crop of the same workload."""
     import oracle
@@ -108,6 +184,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--mode", default="bench", choices=["bench", "copy"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -159,7 +237,11 @@ def main():
                 n64 = lv.density()
                 var["fp32_shifted_vs_fp64_density_rel_err"] = float(np.abs(n_fp32 - n64).max() / np.abs(n64).max())
             lv.close()
+        if not args.no_3d:
+            var["d3q19_512cube_fp32"] = d3q19_leg(stream)
         out["variants"] = var
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, G, n0)
     print(json.dumps(out), flush=True)

@@ -18,10 +18,13 @@ class DropletProblem:
 
     dims: list of square (L, L); n0: concatenated initial densities; centers: (ndom, 2);
     codes: shell codes; tau: per-domain relaxation times; psi_kind / psi_param as in scl.h.
+    equilibrate: if > 0, the first load() relaxes n0 for that many steps with the parameters
+    it is given, and that state becomes the fixed initial state of every later run, so the
+    differentiated window starts from a droplet at mechanical equilibrium.
     """
 
     def __init__(self, dims, n0, centers, codes, tau, nsteps, every, precision, is_bubble=None,
-                 psi_kind=0, psi_param=None, stream=None):
+                 psi_kind=0, psi_param=None, stream=None, equilibrate=0):
         self.lat = Lattice(dims, precision, stream=stream)
         self.n0 = np.ascontiguousarray(n0, dtype=np.float64)
         self.centers = np.asarray(centers, dtype=np.int32)
@@ -30,14 +33,29 @@ class DropletProblem:
         self.nsteps, self.every = int(nsteps), int(every)
         self.is_bubble = is_bubble
         self.psi_kind, self.psi_param = psi_kind, psi_param
+        self.equilibrate = int(equilibrate)
+        self.f0 = None
 
-    def run(self, W, G):
+    def load(self, W, G):
+        """Set the parameters and the initial state of the differentiated window."""
         lat = self.lat
         lat.set_physics(self.tau, G, self.psi_kind, self.psi_param)
         lat.set_stencil(self.codes, W)
         lat.init_density(self.n0)
-        lat.checkpointed_forward(self.nsteps, self.every)
-        return lat.droplet_observables(self.centers, self.is_bubble)
+        if self.equilibrate > 0:
+            if self.f0 is None:
+                lat.step(self.equilibrate)
+                self.f0 = lat.populations()
+            lat.set_populations(self.f0)
+
+    def forward(self):
+        """Checkpointed forward of the window, then the observables of its final state."""
+        self.lat.checkpointed_forward(self.nsteps, self.every)
+        return self.lat.droplet_observables(self.centers, self.is_bubble)
+
+    def run(self, W, G):
+        self.load(W, G)
+        return self.forward()
 
     def vjp(self, g_obs):
         seed, gW_direct, gG_direct = self.lat.droplet_observables_vjp(self.centers, g_obs, self.is_bubble)

@@ -10,7 +10,7 @@ import torch
 
 import oracle
 from oracle import thermo
-from paper_2505_23647_amd import SCL_FP32, SCL_FP64, Lattice, synth
+from paper_2505_23647_amd import SCL_FP32, SCL_FP32_SHIFTED, SCL_FP64, Lattice, synth
 from paper_2505_23647_amd.autograd import DropletObservables, DropletProblem
 from tests.gpu_helpers import E8_2D, coupling, family2d_weights, perm_to_oracle, say
 
@@ -186,3 +186,68 @@ def test_adjoint_requires_checkpointed_forward():
     lat.step(1)  # changes the state: the checkpoints no longer describe it
     with pytest.raises(SclError):
         lat.adjoint(seed_n=np.ones(256))
+
+
+def test_c5_full_size_fd_and_fp32():
+    """The batched droplet workload at full size (16 x 256^2, 2000-step window from relaxed
+    droplets, checkpoints every 45). The loss is strongly curved in W (a 1e-4 relative change of
+    a weight shifts the droplet's equilibrium and its ringing), so central differences carry an
+    O(h^2) truncation error: measured 6e-2 at h = 1e-4 |W|, 6e-4 at 1e-5, 6e-6 at 1e-6. The
+    FP64 adjoint must (a) agree with Richardson-extrapolated differences at h = 1e-6, 5e-7
+    (relative) to 1e-6, and (b) show the difference at h = 1e-4, 1e-5 falling 100-fold per
+    decade (second order, i.e. truncation of the differences, not an adjoint error). FP32
+    adjoint against FP64: measured bound."""
+    import bench
+    say("case: C5 full size")
+    prob, W, G = bench.c5_problem(SCL_FP64)
+    obs = prob.run(W, G)
+    assert np.all(np.isfinite(obs)) and np.all(obs[:, 1] > 0)
+    ts, td = bench.c5_targets(obs)
+    gobs = np.zeros_like(obs)
+    gobs[:, 3] = 2 * (obs[:, 3] - ts)
+    gobs[:, 5] = 2 * (obs[:, 5] - td)
+    gW, gG = prob.vjp(gobs)
+    grad = np.concatenate([gW, gG[:, None]], axis=1)
+
+    def loss(Wp, Gp):
+        o = prob.run(Wp, Gp)
+        return (o[:, 3] - ts) ** 2 + (o[:, 5] - td) ** 2
+
+    def central(q, rel):
+        base = np.abs(W[:, q]) if q < W.shape[1] else np.abs(G)
+        h = rel * np.maximum(base, 1e-2)
+        Wp, Wm, Gp, Gm = W.copy(), W.copy(), G.copy(), G.copy()
+        if q < W.shape[1]:
+            Wp[:, q] += h
+            Wm[:, q] -= h
+        else:
+            Gp = Gp + h
+            Gm = Gm - h
+        return (loss(Wp, Gp) - loss(Wm, Gm)) / (2 * h)
+
+    scale = np.abs(grad).max(axis=1)
+    worst = 0.0
+    for q in range(grad.shape[1]):
+        rich = (4 * central(q, 5e-7) - central(q, 1e-6)) / 3
+        worst = max(worst, float((np.abs(grad[:, q] - rich) / scale).max()))
+        e4 = np.abs(central(q, 1e-4) - grad[:, q]) / scale
+        e5 = np.abs(central(q, 1e-5) - grad[:, q]) / scale
+        assert np.all((e4 / e5 > 60) & (e4 / e5 < 160)), (q, e4, e5)
+    say(f"  fp64 adjoint vs Richardson differences: max rel err over 16 domains {worst:.2e}")
+    assert worst < 1e-6
+    # Float runs: the Jacobian is compared with a common seed dL/dobs (the FP64 one). The loss
+    # values themselves differ: the observables integrate r (P_out - P_T) out to L/2, so
+    # rounding noise in the far field moves delta by ~1e-2 relative, comparable to the residual
+    # delta - delta* of some domains. Measured on MI355X: 4e-4 (shifted), 9e-4 (plain).
+    errs = {}
+    for name, prec in (("fp32_shifted", SCL_FP32_SHIFTED), ("fp32", SCL_FP32)):
+        p32, _, _ = bench.c5_problem(prec)
+        p32.f0 = prob.f0  # same relaxed start
+        o32 = p32.run(W, G)
+        say(f"  {name}: observables max rel diff {float((np.abs(o32 - obs) / np.abs(obs)).max()):.2e}")
+        gW32, gG32 = p32.vjp(gobs)
+        grad32 = np.concatenate([gW32, gG32[:, None]], axis=1)
+        errs[name] = float((np.abs(grad32 - grad).max(axis=1) / scale).max())
+        say(f"  {name} vs fp64 adjoint (common seed): max rel err {errs[name]:.2e}")
+        p32.lat.close()
+    assert errs["fp32_shifted"] < 5e-3 and errs["fp32"] < 1e-2
