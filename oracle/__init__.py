@@ -8,7 +8,7 @@ Sub-modules:
   * ``stencil_algebra`` - exact-rational forcing-stencil algebra (moments, isotropy and
     anisotropy coefficients, projected pressure-tensor coefficients, knobs).
   * ``thermo`` - bulk thermodynamics of the Shan-Chen fluid (critical coupling, coexistence).
-  * ``flat`` - flat-interface observables (sigma_0, z_s, z_e, Tolman length).
+  * ``flat`` - flat-interface observables (sigma_0, z_s, z_e, Tolman length, analytic estimates).
 """
 from __future__ import annotations
 
