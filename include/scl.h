@@ -163,8 +163,8 @@ scl_status scl_droplet_observables(scl_lattice lat, const int32_t* center, const
 /* Tiling of the fused step.
  *   2D: strip = output lanes per workgroup (64, 128 or 256); seg = rows one workgroup marches
  *       (>= 1); cpl = sites per lane (1, or 2 for vector accesses, which needs every domain
- *       width even; 0 = 2 when possible).
- *   3D: strip = tile index (1: 32x8, 2: 32x16, 3: 32x32 lanes, float arithmetic only);
+ *       width even; 0 = automatic: one site per lane).
+ *   3D: strip = tile index (1: 64x4, 2: 64x8, 3: 32x8 output sites per workgroup);
  *       seg = planes one workgroup marches; cpl is ignored.
  * 0 keeps the current value (for cpl: automatic). */
 scl_status scl_set_tiling(scl_lattice lat, int32_t strip, int32_t seg, int32_t cpl);

@@ -13,6 +13,9 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse a*b + c only where one source expression says so: every code variant of a kernel
+    # then rounds the same way
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
 ]
 

@@ -54,7 +54,7 @@ const int SET3N[2] = {3, 7};
 
 // 3D tile shapes selectable through scl_set_tiling(strip = index).
 struct Tile3 { int tx, ty; };
-const Tile3 TILES3[4] = {{0, 0}, {32, 8}, {32, 16}, {32, 32}};
+const Tile3 TILES3[4] = {{0, 0}, {64, 4}, {64, 8}, {32, 8}};
 
 }  // namespace
 
@@ -85,7 +85,7 @@ struct scl_lattice_s {
   int nitems = 0;
   bool dirty_doms = true, dirty_items = true;
   // tiling
-  int strip = 128, seg = 0;        // 2D: output lanes per workgroup, rows per item (0 = auto)
+  int strip = 256, seg = 0;        // 2D: output lanes per workgroup, rows per item (0 = auto)
   int cpl_req = 0;                 // 2D: sites per lane requested (0 = auto)
   int cpl = 1;                     // 2D: sites per lane in use
   int tile3 = 2, seg3 = 0;         // 3D: tile index, planes per item (0 = auto)
@@ -96,6 +96,8 @@ struct scl_lattice_s {
   // readout scratch (double)
   double *d_n = nullptr, *d_psi = nullptr, *d_j = nullptr, *d_F = nullptr, *d_tmp = nullptr;
   double* d_part = nullptr;
+  void* d_psi3 = nullptr;          // 3D: psi of every site (arithmetic precision), pass 1 -> pass 2
+  std::vector<DomDev> h_doms;      // host copy of d_doms
   size_t part_cap = 0;
   int64_t steps = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -152,7 +154,6 @@ VecTable full_table(const scl_lattice_s* L) {
 
 scl_status build_items(scl_lattice_s* L) {
   std::vector<WorkItem> items;
-  const int R = stencil_reach(L);
   if (L->d == 2) {
     // sites per lane (two need every domain width even)
     bool even = true;
@@ -163,10 +164,10 @@ scl_status build_items(scl_lattice_s* L) {
     L->cpl = L->cpl_req ? L->cpl_req : 1;
     if (L->cpl == 2 && !even) return fail(SCL_E_INVALID, "two sites per lane need even domain widths");
     const int outw = L->strip * L->cpl;
-    // rows per item: measured best on MI355X with 128-lane strips (4096^2, 24 vectors):
-    // 32 for 4- and 2-byte storage, 128 for FP64
+    // rows per item: measured best on MI355X with 256-lane strips (4096^2, 24 vectors): 32
+    // for every storage width (within 2% of the best for FP16)
     int seg = L->seg;
-    if (seg <= 0) seg = L->prec == SCL_FP64 ? 128 : 32;
+    if (seg <= 0) seg = 32;
     // Order: bands of BAND row ranges; within a band, strip by strip, the ranges of the band
     // in order. The device hands each XCD a contiguous eighth of this list, so an XCD works on
     // a compact block of neighbouring strips and ranges whose shared halos meet in its L2.
@@ -187,7 +188,7 @@ scl_status build_items(scl_lattice_s* L) {
     }
   } else {
     const Tile3 t = TILES3[L->tile3];
-    const int ox = t.tx - 2 * R, oy = t.ty - 2 * R;
+    const int ox = t.tx, oy = t.ty;
     int seg = L->seg3;
     if (seg <= 0) {
       long long work = 0;
@@ -195,16 +196,20 @@ scl_status build_items(scl_lattice_s* L) {
         work += (long long)((L->nx[k] + ox - 1) / ox) * ((L->ny[k] + oy - 1) / oy) * L->nz[k];
       seg = (int)std::max<long long>(16, (work + 2047) / 2048);
     }
-    for (int k = 0; k < L->ndom; ++k)
-      for (int z0 = 0; z0 < L->nz[k]; z0 += seg)
-        for (int y0 = 0; y0 < L->ny[k]; y0 += oy)
-          for (int x0 = 0; x0 < L->nx[k]; x0 += ox) {
+    // Order: tile by tile (x fastest), the z-ranges of a tile together, alternating their
+    // marching direction, so that neighbouring tiles and ranges land on the same XCD.
+    for (int k = 0; k < L->ndom; ++k) {
+      const int nzr = (L->nz[k] + seg - 1) / seg;
+      for (int y0 = 0; y0 < L->ny[k]; y0 += oy)
+        for (int x0 = 0; x0 < L->nx[k]; x0 += ox)
+          for (int zr = 0; zr < nzr; ++zr) {
             WorkItem w{};
             w.dom = k; w.x0 = x0; w.y0 = y0; w.y1 = std::min(y0 + oy, L->ny[k]);
-            w.z0 = z0; w.z1 = std::min(z0 + seg, L->nz[k]);
-            w.dir = 1;
+            w.z0 = zr * seg; w.z1 = std::min(zr * seg + seg, L->nz[k]);
+            w.dir = (zr % 2 == 0) ? 1 : -1;
             items.push_back(w);
           }
+    }
   }
   if (L->d_items) { HIPCHK(hipFree(L->d_items)); L->d_items = nullptr; }
   HIPCHK(hipMalloc(&L->d_items, sizeof(WorkItem) * items.size()));
@@ -219,6 +224,7 @@ scl_status sync_params(scl_lattice_s* L) {
     std::vector<DomDev> v = host_doms(L);
     if (!L->d_doms) HIPCHK(hipMalloc(&L->d_doms, sizeof(DomDev) * L->ndom));
     HIPCHK(hipMemcpyAsync(L->d_doms, v.data(), sizeof(DomDev) * L->ndom, hipMemcpyHostToDevice, L->stream));
+    L->h_doms = v;
     HIPCHK(hipStreamSynchronize(L->stream));
     L->dirty_doms = false;
   }
@@ -242,11 +248,14 @@ hipError_t launch2d(scl_lattice_s* L, const void* fin, void* fout, MacroRec<M> r
   const dim3 grid(8 * per);
 #define SCL_2D_CASE(SETV, NOV, CPLV)                                                                  \
   if (L->set == SETV && L->strip == NOV && L->cpl == CPLV) {                                           \
-    constexpr int nt = NOV + 2 * Halo2<SETV, CPLV>::HL;                                                \
-    if (record)                                                                                        \
-      hipLaunchKernelGGL((k_step2d<S, M, SETV, NOV, CPLV, SHIFT, true>), grid, dim3(nt), 0, L->launch,  \
-                         (const S*)fin, (S*)fout, L->d_doms, L->d_items, L->nitems, rec);              \
-    else                                                                                               \
+    constexpr int nt = NOV;                                                                            \
+    if constexpr (!std::is_same<S, _Float16>::value) {                                                 \
+      if (record) {                                                                                    \
+        hipLaunchKernelGGL((k_step2d<S, M, SETV, NOV, CPLV, SHIFT, true>), grid, dim3(nt), 0, L->launch, \
+                           (const S*)fin, (S*)fout, L->d_doms, L->d_items, L->nitems, rec);            \
+        return hipGetLastError();                                                                      \
+      }                                                                                                \
+    }                                                                                                  \
       hipLaunchKernelGGL((k_step2d<S, M, SETV, NOV, CPLV, SHIFT, false>), grid, dim3(nt), 0, L->launch, \
                          (const S*)fin, (S*)fout, L->d_doms, L->d_items, L->nitems, rec);              \
     return hipGetLastError();                                                                          \
@@ -261,17 +270,23 @@ hipError_t launch2d(scl_lattice_s* L, const void* fin, void* fout, MacroRec<M> r
 
 template <class S, class M, bool SHIFT>
 hipError_t launch3d(scl_lattice_s* L, const void* fin, void* fout) {
-  const dim3 grid(L->nitems);
+  // pass 1: psi of every site, domain by domain
+  for (int k = 0; k < L->ndom; ++k) {
+    const DomDev& dd = L->h_doms[k];
+    hipLaunchKernelGGL((k_psi3d<S, M, SHIFT>), dim3((L->nx[k] + 255) / 256, L->ny[k], L->nz[k]), dim3(256), 0,
+                       L->launch, (const S*)fin, (M*)L->d_psi3, dd);
+  }
+  // pass 2: force, collision, streaming over the work items
+  const int per = (L->nitems + 7) / 8;
+  const dim3 grid(8 * per);
 #define SCL_3D_CASE(SETV, TI, TXV, TYV)                                                          \
   if (L->set == SETV && L->tile3 == TI) {                                                          \
     hipLaunchKernelGGL((k_step3d<S, M, SETV, TXV, TYV, SHIFT>), grid, dim3(TXV * TYV), 0, L->launch, \
-                       (const S*)fin, (S*)fout, L->d_doms, L->d_items);                           \
+                       (const S*)fin, (S*)fout, (const M*)L->d_psi3, L->d_doms, L->d_items, L->nitems); \
     return hipGetLastError();                                                                     \
   }
-  SCL_3D_CASE(0, 1, 32, 8) SCL_3D_CASE(0, 2, 32, 16) SCL_3D_CASE(1, 1, 32, 8) SCL_3D_CASE(1, 2, 32, 16)
-  if (sizeof(M) == 4) {
-    SCL_3D_CASE(0, 3, 32, 32) SCL_3D_CASE(1, 3, 32, 32)
-  }
+  SCL_3D_CASE(0, 1, 64, 4) SCL_3D_CASE(0, 2, 64, 8) SCL_3D_CASE(0, 3, 32, 8)
+  SCL_3D_CASE(1, 1, 64, 4) SCL_3D_CASE(1, 2, 64, 8) SCL_3D_CASE(1, 3, 32, 8)
 #undef SCL_3D_CASE
   return hipErrorInvalidValue;
 }
@@ -526,6 +541,12 @@ scl_status scl_create(scl_velset vs, scl_precision prec, int32_t ndom, const int
     const int x = dims[3 * k], y = dims[3 * k + 1], z = dims[3 * k + 2];
     if (x < 1 || y < 1 || z < 1) return fail(SCL_E_INVALID, "every extent must be >= 1");
     if (L->d == 2 && z != 1) return fail(SCL_E_INVALID, "D2Q9 domains need nz = 1");
+    // the 2D step addresses a row through a buffer descriptor with 31-bit byte offsets
+    if (L->d == 2 && (long long)(x + 1) * 8 >= (1ll << 31)) return fail(SCL_E_INVALID, "D2Q9 domain width too large");
+    // the 3D step addresses a z-plane the same way
+    if (L->d == 3 && (long long)x * y * 8 >= (1ll << 31)) return fail(SCL_E_INVALID, "D3Q19 domain x-y plane too large");
+    // the 3D psi pass launches a (x chunks, ny, nz) grid
+    if (L->d == 3 && (y > 65535 || z > 65535)) return fail(SCL_E_INVALID, "D3Q19 domain ny and nz must be <= 65535");
     L->nx.push_back(x); L->ny.push_back(y); L->nz.push_back(z);
     L->off.push_back(tot);
     tot += (long long)x * y * z;
@@ -544,6 +565,12 @@ scl_status scl_create(scl_velset vs, scl_precision prec, int32_t ndom, const int
     (void)hipGetLastError();
     return fail(SCL_E_NOMEM, "population buffers do not fit in device memory");
   }
+  if (L->d == 3 && hipMalloc(&L->d_psi3, (size_t)tot * (prec == SCL_FP64 ? 8 : 4)) != hipSuccess) {
+    (void)hipFree(L->A);
+    (void)hipFree(L->B);
+    (void)hipGetLastError();
+    return fail(SCL_E_NOMEM, "the psi array does not fit in device memory");
+  }
   HIPCHK(hipEventCreate(&L->ev0));
   HIPCHK(hipEventCreate(&L->ev1));
   *out = L.release();
@@ -554,7 +581,8 @@ scl_status scl_destroy(scl_lattice L) {
   if (!L) return SCL_OK;
   drop_graph(L);
   adjoint_free(L->adj);
-  void* ptrs[] = {L->A, L->B, L->d_doms, L->d_items, L->d_n, L->d_psi, L->d_j, L->d_F, L->d_tmp, L->d_part};
+  void* ptrs[] = {L->A, L->B, L->d_doms, L->d_items, L->d_n, L->d_psi, L->d_j, L->d_F, L->d_tmp, L->d_part,
+                  L->d_psi3};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (L->cap) (void)hipStreamDestroy(L->cap);
@@ -891,8 +919,6 @@ scl_status scl_set_tiling(scl_lattice L, int32_t strip, int32_t seg, int32_t cpl
   if (L->d == 2) {
     if (strip != 0 && strip != 64 && strip != 128 && strip != 256) return fail(SCL_E_INVALID, "2D strip must be 64, 128 or 256");
     if (cpl > 2) return fail(SCL_E_INVALID, "sites per lane must be 1 or 2 (0 = automatic)");
-    if (cpl == 2 && L->prec == SCL_FP16S_FP32)
-      return fail(SCL_E_UNSUPPORTED, "two sites per lane are not offered for FP16 storage");
     if (cpl == 2)
       for (int k = 0; k < L->ndom; ++k)
         if (L->nx[k] % 2) return fail(SCL_E_INVALID, "two sites per lane need even domain widths");
@@ -900,8 +926,7 @@ scl_status scl_set_tiling(scl_lattice L, int32_t strip, int32_t seg, int32_t cpl
     if (seg) L->seg = seg;
     L->cpl_req = cpl;
   } else {
-    if (strip > 3) return fail(SCL_E_INVALID, "3D tile index must be 1 (32x8), 2 (32x16) or 3 (32x32)");
-    if (strip == 3 && L->prec == SCL_FP64) return fail(SCL_E_INVALID, "the 32x32 tile is for float arithmetic");
+    if (strip > 3) return fail(SCL_E_INVALID, "3D tile index must be 1 (64x4), 2 (64x8) or 3 (32x8)");
     if (strip) L->tile3 = strip;
     if (seg) L->seg3 = seg;
   }
@@ -953,7 +978,6 @@ scl_status scl_tune(scl_lattice L, const char* cache_path) {
       for (int sg : {8, 16, 32, 64, 128}) cands.push_back({st, sg});
   } else {
     for (int t : {1, 2, 3}) {
-      if (t == 3 && L->prec == SCL_FP64) continue;
       for (int sg : {8, 16, 32, 64}) cands.push_back({t, sg});
     }
   }

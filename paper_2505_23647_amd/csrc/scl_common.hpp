@@ -7,6 +7,13 @@
 #include <type_traits>
 #include <utility>
 
+// cache policy bits of the steps' population stores: non-temporal (the new state is not
+// read again within the step, so it should not push out rows that neighbouring work items
+// are about to re-read)
+#ifndef SCL_STORE_AUX
+#define SCL_STORE_AUX 2
+#endif
+
 namespace scl {
 
 constexpr int MAX_SHELLS = 8;   // weight slots per domain
@@ -188,9 +195,11 @@ template <int VS> __host__ __device__ constexpr int opp(int i) {
 // written as f*_i = (1 - omega) f_i + A +- B for each pair (i, opposite of i): A collects the
 // terms even in xi, B the odd ones. base = n for plain storage; for shifted storage (f holds
 // f - w rho0) base = n - rho0 = sum of the stored values, which subtracts w rho0 from f^eq.
-template <int VS, class M>
-__device__ __forceinline__ void collide(const M* f, M base, M nn, M ux, M uy, M uz, M Fx, M Fy, M Fz, M omega,
-                                        M kappa, M* fo) {
+// emit(i, value) receives each post-collision value (pairs in turn), so a caller can store it
+// at once instead of holding all Q.
+template <int VS, class M, class Emit>
+__device__ __forceinline__ void collide_emit(const M* f, M base, M nn, M ux, M uy, M uz, M Fx, M Fy, M Fz,
+                                             M omega, M kappa, Emit&& emit) {
   using V = Vel<VS>;
   constexpr int Q = V::Q;
   const M uu15 = M(1.5) * (ux * ux + uy * uy + uz * uz);  // u.u / (2 c^2)
@@ -200,7 +209,7 @@ __device__ __forceinline__ void collide(const M* f, M base, M nn, M ux, M uy, M 
   const M obase = omega * base;
   {
     constexpr M w = M(V::w(0));
-    fo[0] = om1 * f[0] + (w * (obase - on * uu15) - (kappa * w) * uF3);
+    emit(0, om1 * f[0] + (w * (obase - on * uu15) - (kappa * w) * uF3));
   }
   static_for<Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
@@ -216,10 +225,73 @@ __device__ __forceinline__ void collide(const M* f, M base, M nn, M ux, M uy, M 
       const M Se = M(9) * xu * xF - uF3;
       const M A = w * (obase + on * E) + (kappa * w) * Se;
       const M B = (M(3) * w) * (on * xu + kappa * xF);
-      fo[i] = om1 * f[i] + (A + B);
-      fo[ib] = om1 * f[ib] + (A - B);
+      emit(i, om1 * f[i] + (A + B));
+      emit(ib, om1 * f[ib] + (A - B));
     }
   });
+}
+
+template <int VS, class M>
+__device__ __forceinline__ void collide(const M* f, M base, M nn, M ux, M uy, M uz, M Fx, M Fy, M Fz, M omega,
+                                        M kappa, M* fo) {
+  collide_emit<VS, M>(f, base, nn, ux, uy, uz, Fx, Fy, Fz, omega, kappa, [&](int i, M v) { fo[i] = v; });
+}
+
+// ------------------------------------------------------------------ buffer access
+// The step reads and writes through buffer instructions: the row's base address lives in a
+// (uniform) buffer descriptor, the lane supplies a 32-bit byte offset that stays fixed for the
+// whole march, and the hardware range check bounds every access to the row.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+
+__device__ __forceinline__ Rsrc mkrsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// CPL stored values at byte offset voff of the buffer r, converted to M.
+template <class S, class M, int CPL> __device__ __forceinline__ void ldb(Rsrc r, uint32_t voff, M* out) {
+  constexpr int B = (int)sizeof(S) * CPL;
+  S t[CPL];
+  if constexpr (B == 2) {
+    const auto u = __builtin_amdgcn_raw_buffer_load_b16(r, voff, 0, 0);
+    __builtin_memcpy(t, &u, B);
+  } else if constexpr (B == 4) {
+    const auto u = __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0);
+    __builtin_memcpy(t, &u, B);
+  } else if constexpr (B == 8) {
+    const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0);
+    __builtin_memcpy(t, &u, B);
+  } else {
+    static_assert(B == 16, "unsupported access width");
+    const auto u = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
+    __builtin_memcpy(t, &u, B);
+  }
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) out[c] = static_cast<M>(t[c]);
+}
+
+template <class S, class M, int CPL, int AUX = 0>
+__device__ __forceinline__ void stb(Rsrc r, uint32_t voff, const M* in) {
+  constexpr int B = (int)sizeof(S) * CPL;
+  S t[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) t[c] = static_cast<S>(in[c]);
+  if constexpr (B == 2) {
+    unsigned short u;
+    __builtin_memcpy(&u, t, B);
+    __builtin_amdgcn_raw_buffer_store_b16(u, r, voff, 0, AUX);
+  } else if constexpr (B == 4) {
+    uint32_t u;
+    __builtin_memcpy(&u, t, B);
+    __builtin_amdgcn_raw_buffer_store_b32(u, r, voff, 0, AUX);
+  } else if constexpr (B == 8) {
+    uint32_t u __attribute__((ext_vector_type(2)));
+    __builtin_memcpy(&u, t, B);
+    __builtin_amdgcn_raw_buffer_store_b64(u, r, voff, 0, AUX);
+  } else {
+    uint32_t u __attribute__((ext_vector_type(4)));
+    __builtin_memcpy(&u, t, B);
+    __builtin_amdgcn_raw_buffer_store_b128(u, r, voff, 0, AUX);
+  }
 }
 
 }  // namespace scl

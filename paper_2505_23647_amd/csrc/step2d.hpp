@@ -22,6 +22,11 @@
 #pragma once
 #include "scl_common.hpp"
 
+// rows whose loads are kept in flight ahead of the row being reduced to psi (1 or 2)
+#ifndef SCL_STEP2D_PF
+#define SCL_STEP2D_PF 1
+#endif
+
 namespace scl {
 
 template <class S, int CPL> struct VecOf;
@@ -55,53 +60,31 @@ template <class S, class M, int CPL> __device__ __forceinline__ void stv(S* p, c
 }
 
 // Values at row positions xw + dx .. xw + dx + CPL - 1 (dx in {-1, 0, 1}) of a periodic row of
-// nx values; xw and nx are multiples of CPL, so only the first or last element can wrap.
-// WRAP = false promises that xw + dx .. xw + dx + CPL - 1 lie inside the row: a plain load.
+// nx values. The descriptor r starts one value before the row (so every offset is
+// non-negative) and spans nx + 1 values. Without WRAP the positions lie inside the row: the
+// lane's byte offset xb = xw * sizeof(S) plus the constant (dx + 1) * sizeof(S). With WRAP
+// (strips at the periodic seam) each value's position is wrapped on its own.
 template <class S, class M, int CPL, bool WRAP>
-__device__ __forceinline__ void ld_shift(const S* row, int xw, int nx, int dx, M* out) {
+__device__ __forceinline__ void ld_row(Rsrc r, uint32_t xb, int xw, int nx, int dx, bool active, M* out) {
   if constexpr (!WRAP) {
-    ldv<S, M, CPL>(row + xw + dx, out);
-  } else if constexpr (CPL == 1) {
-    out[0] = static_cast<M>(row[wrapi(xw + dx, nx)]);
+    ldb<S, M, CPL>(r, xb + (uint32_t)((dx + 1) * (int)sizeof(S)), out);
   } else {
-    if (dx == 0) {
-      ldv<S, M, CPL>(row + xw, out);
-    } else if (dx < 0) {
-      M v[CPL];
-      ldv<S, M, CPL>(row + (xw > 0 ? xw - 1 : 0), v);
-      if (xw > 0) {
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) out[c] = v[c];
-      } else {
-        out[0] = static_cast<M>(row[nx - 1]);
-#pragma unroll
-        for (int c = 1; c < CPL; ++c) out[c] = v[c - 1];
-      }
-    } else {
-      M v[CPL];
-      const bool wrap = xw + CPL >= nx;
-      ldv<S, M, CPL>(row + (wrap ? xw : xw + 1), v);
-      if (!wrap) {
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) out[c] = v[c];
-      } else {
-#pragma unroll
-        for (int c = 0; c < CPL - 1; ++c) out[c] = v[c + 1];
-        out[CPL - 1] = static_cast<M>(row[0]);
-      }
-    }
+    for (int c = 0; c < CPL; ++c)
+      ldb<S, M, 1>(r, active ? (uint32_t)(wrapi(xw + c + dx, nx) + 1) * sizeof(S) : 0x80000000u, out + c);
   }
 }
 
-// NO output lanes (a multiple of 64) + 2 HL halo lanes.
+// Halo geometry: HX = R rounded up to CPL halo columns on each side of a strip, covered by
+// HL = HX / CPL halo lanes per side.
 template <int SET, int CPL> struct Halo2 {
   static constexpr int R = Shells<2, SET>::R;
-  static constexpr int HX = ((R + CPL - 1) / CPL) * CPL;  // halo columns per side
-  static constexpr int HL = HX / CPL;                     // halo lanes per side
+  static constexpr int HX = ((R + CPL - 1) / CPL) * CPL;
+  static constexpr int HL = HX / CPL;
 };
 
 template <class S, class M, int SET, int NO, int CPL, bool SHIFT, bool REC>
-__global__ void __launch_bounds__((NO + 2 * Halo2<SET, CPL>::HL))
+__global__ void __launch_bounds__(NO)
 k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restrict__ doms,
          const WorkItem* __restrict__ items, int nitems, MacroRec<M> rec) {
   using V = Vel<0>;
@@ -111,8 +94,12 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
   constexpr int HX = Halo2<SET, CPL>::HX;
   constexpr int HL = Halo2<SET, CPL>::HL;
   constexpr int RING = 2 * R + 2;
-  constexpr int NSLOT = R + 1;
-  constexpr int WIDTH = CPL * NO + 2 * HX;  // ring row length (sites)
+  // rows in registers: R + 1 waiting for their collision + PF whose loads are in flight; the
+  // unrolled loop cycles through NSLOT register sets (a multiple of PF + 1, the halo's sets)
+  constexpr int PF = SCL_STEP2D_PF;
+  constexpr int NSLOT = (R + 1 + PF + PF) / (PF + 1) * (PF + 1);
+  constexpr int WIDTH = CPL * NO + 2 * HX;      // ring row length (sites)
+  static_assert(2 * HL <= 64, "halo lanes must fit in the first wave");
 
   __shared__ M psis[RING * WIDTH];
 
@@ -134,126 +121,165 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
 #pragma unroll
   for (int s = 0; s < SH::NS; ++s) Wv[s] = M(dm.W[s]);
 
-  // lane -> first site X of the lane and its position q in a ring row
+  // Every lane owns CPL output sites X .. X + CPL - 1 (ring position q). Lanes 0 .. 2 HL - 1
+  // also load one halo group (position Xh, ring position qh): HL groups left of the strip and
+  // HL right of it. For a strip cut short by the domain edge (xend < x0 + CPL NO), output lanes
+  // past xend supply the right halo instead.
   const int lane = threadIdx.x;
-  int X, q;
-  if (lane < NO) {
-    X = it.x0 + CPL * lane;
-    q = HX + CPL * lane;
-  } else if (lane < NO + HL) {
-    X = it.x0 - HX + CPL * (lane - NO);
-    q = CPL * (lane - NO);
-  } else {
-    X = it.x0 + CPL * NO + CPL * (lane - NO - HL);
-    q = HX + CPL * NO + CPL * (lane - NO - HL);
-  }
-  const int xend = min(it.x0 + CPL * NO, nx);     // end of this strip's outputs
-  const bool outl = lane < NO && X < xend;
-  const bool need = X < xend + HX;                 // psi of this lane is read by an output
-  const int xw = wrapi(X, nx);
+  const int X = it.x0 + CPL * lane;
+  const int q = HX + CPL * lane;
+  const int xend = min(it.x0 + CPL * NO, nx);
+  const bool outl = X < xend;
+  const bool need = X < xend + HX;
+  const int Xh = lane < HL ? it.x0 - HX + CPL * lane : it.x0 + CPL * NO + CPL * (lane - HL);
+  const int qh = lane < HL ? CPL * lane : HX + CPL * NO + CPL * (lane - HL);
+  const bool needh = lane < 2 * HL && Xh < xend + HX;
+  const int xw = wrapi(X, nx), xwh = wrapi(Xh, nx);
+  // Every memory instruction of the march is issued by every lane at every step, so that the
+  // compiler can keep the next row's loads in flight (a load under a branch would force it to
+  // wait for everything). A lane or row with nothing to move gets an offset past the end of
+  // the buffer: the hardware range check then drops the access without touching memory.
+  constexpr uint32_t OFF = 0x80000000u;
+  const uint32_t xb = need ? (uint32_t)xw * sizeof(S) : OFF;
+  const uint32_t xbh = needh ? (uint32_t)xwh * sizeof(S) : OFF;
+  const uint32_t xbo = outl ? (uint32_t)xw * sizeof(S) : OFF;
+  const uint32_t xbm = outl ? (uint32_t)xw * sizeof(M) : OFF;
+  const uint32_t rowbytes = (uint32_t)(nx + 1) * sizeof(S);  // a row plus the value before it
 
   const int dir = it.dir;
-  const int total = (it.y1 - it.y0) + 2 * R;
+  const int total = (it.y1 - it.y0) + 2 * R;  // marching steps: rows loaded
+  const int steps = (total + NSLOT - 1) / NSLOT * NSLOT;
   const int rstart = dir > 0 ? it.y0 - R : it.y1 - 1 + R;
-  const int rbase = it.y0 - R - RING;              // ring row of row r: (r - rbase) % RING
+  const int rbase = it.y0 - R - RING - NSLOT;  // ring row of row r: (r - rbase) % RING
   // Strips whose pulls never cross the periodic seam in x (all but the first and last of a
   // domain) take a branch-free path; the others resolve the seam per lane.
   const bool seam = it.x0 - HX - 1 < 0 || it.x0 + CPL * NO + HX + 1 > nx;
   auto march = [&](auto SEAM) {
-  constexpr bool WRAP = decltype(SEAM)::value;
-  M fr[NSLOT][Q][CPL];
-
-  for (int k0 = 0; k0 < total; k0 += NSLOT) {
-    static_for<NSLOT>([&](auto J) {
-      constexpr int j = decltype(J)::value;
-      const int k = k0 + j;
-      if (k < total) {
-        const int r = rstart + dir * k;
-        // ---------------- 1. pull row r, psi into the ring
-        if (need) {
-          const int rw = wrapi(r, ny), rm = wrapi(r - 1, ny), rp = wrapi(r + 1, ny);
+    constexpr bool WRAP = decltype(SEAM)::value;
+    // fr: populations of the rows between their load and their collision (R + 1 rows) plus
+    // the row whose loads are in flight; hr: the same for the halo group (current + next).
+    M fr[NSLOT][Q][CPL];
+    M hr[PF + 1][Q][CPL];
 #pragma unroll
-          for (int i = 0; i < Q; ++i) {
-            const int cy = V::cy(i), cx = V::cx(i);
-            const int srow = cy == 1 ? rm : (cy == -1 ? rp : rw);
-            ld_shift<S, M, CPL, WRAP>(fb + (long long)i * cells + (long long)srow * nx, xw, nx, -cx, fr[j][i]);
-          }
+    for (int a = 0; a < NSLOT; ++a)
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) fr[a][i][c] = M(0);
+
+    // Loads of marching step k (row r) into register set J: the nine populations streaming
+    // into row r, f_i(x, t) = f*_i(x - xi_i, t - 1). Steps past the last row load nothing.
+    auto issue = [&](int k, auto J) {
+      constexpr int j = decltype(J)::value;
+      const int r = rstart + dir * k;
+      const uint32_t rowoff = k < total ? 0u : OFF;
+      const long long rowo[3] = {(long long)wrapi(r - 1, ny) * nx, (long long)wrapi(r, ny) * nx,
+                                 (long long)wrapi(r + 1, ny) * nx};
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const Rsrc rs = mkrsrc(fb + (long long)i * cells + rowo[1 - V::cy(i)] - 1, rowbytes);
+        ld_row<S, M, CPL, WRAP>(rs, xb | rowoff, xw, nx, -V::cx(i), need && k < total, fr[j % NSLOT][i]);
+        ld_row<S, M, CPL, WRAP>(rs, xbh | rowoff, xwh, nx, -V::cx(i), needh && k < total, hr[j % (PF + 1)][i]);
+      }
+    };
+
+    issue(0, std::integral_constant<int, 0>{});
+    if constexpr (PF > 1) issue(1, std::integral_constant<int, 1>{});
+    for (int k0 = 0; k0 < steps; k0 += NSLOT) {
+      static_for<NSLOT>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        const int k = k0 + j;
+        // ---------------- 1. start the next row's loads, then psi of row r into the ring
+        issue(k + PF, std::integral_constant<int, j + PF>{});
+        const int r = rstart + dir * k;
+        M* ringrow = psis + ((r - rbase) % RING) * WIDTH;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+          M sum = M(0);
+#pragma unroll
+          for (int i = 0; i < Q; ++i) sum += fr[j][i][c];
+          const M p = psi_eval<M>(SHIFT ? rho0 + sum : sum, kind, eps, inv_eps);
+          if (need) ringrow[q + c] = p;
+        }
+        if (needh) {
 #pragma unroll
           for (int c = 0; c < CPL; ++c) {
             M sum = M(0);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) sum += fr[j][i][c];
-            const M n = SHIFT ? rho0 + sum : sum;
-            psis[((r - rbase) % RING) * WIDTH + q + c] = psi_eval<M>(n, kind, eps, inv_eps);
+            for (int i = 0; i < Q; ++i) sum += hr[j % (PF + 1)][i][c];
+            ringrow[qh + c] = psi_eval<M>(SHIFT ? rho0 + sum : sum, kind, eps, inv_eps);
           }
         }
         __syncthreads();
 
-        // ---------------- 2. collide row crow = r - R (marching order), output lanes only
-        if (k >= 2 * R && outl) {
-          constexpr int js = (j + NSLOT - R) % NSLOT;  // register set of that row
-          const int crow = r - dir * R;
-          int so[2 * R + 1];                           // ring row of crow + dy, dy = o - R
+        // ---------------- 2. collide row crow = r - R (marching order); every lane computes,
+        // only output lanes of rows of this item store.
+        constexpr int js = (j + NSLOT - R) % NSLOT;  // register set of that row
+        const int crow = r - dir * R;
+        const bool rowok = k >= 2 * R && k < total;
+        const M* so[2 * R + 1];                      // ring rows of crow + dy, dy = o - R
 #pragma unroll
-          for (int o = 0; o <= 2 * R; ++o) so[o] = ((crow - R + o - rbase) % RING) * WIDTH;
-          const long long o_ = (long long)wrapi(crow, ny) * nx + xw;
-          M out[Q][CPL];
-          M recv[5][CPL];
+        for (int o = 0; o <= 2 * R; ++o) so[o] = psis + ((crow - R + o - rbase) % RING) * WIDTH;
+        const long long orow = (long long)wrapi(crow, ny) * nx;
+        M out[Q][CPL];
+        M recv[5][CPL];
 #pragma unroll
-          for (int c = 0; c < CPL; ++c) {
-            const int qc = q + c;
-            const M psic = psis[so[R] + qc];
-            // force of eq. (sc_f) over +-pairs, summed shell by shell before the weight
-            M dxs[SH::NS], dys[SH::NS];
+        for (int c = 0; c < CPL; ++c) {
+          const int qc = q + c;
+          const M psic = so[R][qc];
+          // force of eq. (sc_f) over +-pairs, summed shell by shell before the weight
+          M dxs[SH::NS], dys[SH::NS];
 #pragma unroll
-            for (int s = 0; s < SH::NS; ++s) { dxs[s] = M(0); dys[s] = M(0); }
+          for (int s = 0; s < SH::NS; ++s) { dxs[s] = M(0); dys[s] = M(0); }
 #pragma unroll
-            for (int h = 0; h < SH::NH; ++h) {
-              const HalfVec hv = SH::h(h);
-              const M d = psis[so[R + hv.y] + qc + hv.x] - psis[so[R - hv.y] + qc - hv.x];
-              if (hv.x != 0) dxs[hv.slot] += M(hv.x) * d;
-              if (hv.y != 0) dys[hv.slot] += M(hv.y) * d;
-            }
-            M ax = M(0), ay = M(0);
-#pragma unroll
-            for (int s = 0; s < SH::NS; ++s) { ax += Wv[s] * dxs[s]; ay += Wv[s] * dys[s]; }
-            const M Fx = gpre * psic * ax;
-            const M Fy = gpre * psic * ay;
-            M f[Q];
-            M sum = M(0), jx = M(0), jy = M(0);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-              f[i] = fr[js][i][c];
-              sum += f[i];
-              if (V::cx(i) != 0) jx += M(V::cx(i)) * f[i];
-              if (V::cy(i) != 0) jy += M(V::cy(i)) * f[i];
-            }
-            const M nn = SHIFT ? rho0 + sum : sum;
-            const M inv_n = rcp<M>(nn);
-            const M ux = (jx + M(0.5) * Fx) * inv_n;
-            const M uy = (jy + M(0.5) * Fy) * inv_n;
-            M fo[Q];
-            collide<0, M>(f, SHIFT ? sum : nn, nn, ux, uy, M(0), Fx, Fy, M(0), omega, kappa, fo);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) out[i][c] = fo[i];
-            if (REC) {
-              recv[0][c] = nn; recv[1][c] = jx; recv[2][c] = jy; recv[3][c] = Fx; recv[4][c] = Fy;
-            }
+          for (int h = 0; h < SH::NH; ++h) {
+            const HalfVec hv = SH::h(h);
+            const M d = so[R + hv.y][qc + hv.x] - so[R - hv.y][qc - hv.x];
+            if (hv.x != 0) dxs[hv.slot] += M(hv.x) * d;
+            if (hv.y != 0) dys[hv.slot] += M(hv.y) * d;
           }
+          M ax = M(0), ay = M(0);
 #pragma unroll
-          for (int i = 0; i < Q; ++i) stv<S, M, CPL>(ob + (long long)i * cells + o_, out[i]);
+          for (int s = 0; s < SH::NS; ++s) { ax += Wv[s] * dxs[s]; ay += Wv[s] * dys[s]; }
+          const M Fx = gpre * psic * ax;
+          const M Fy = gpre * psic * ay;
+          M f[Q];
+          M sum = M(0), jx = M(0), jy = M(0);
+#pragma unroll
+          for (int i = 0; i < Q; ++i) {
+            f[i] = fr[js][i][c];
+            sum += f[i];
+            if (V::cx(i) != 0) jx += M(V::cx(i)) * f[i];
+            if (V::cy(i) != 0) jy += M(V::cy(i)) * f[i];
+          }
+          const M nn = SHIFT ? rho0 + sum : sum;
+          const M inv_n = rcp<M>(nn);
+          const M ux = (jx + M(0.5) * Fx) * inv_n;
+          const M uy = (jy + M(0.5) * Fy) * inv_n;
+          M fo[Q];
+          collide<0, M>(f, SHIFT ? sum : nn, nn, ux, uy, M(0), Fx, Fy, M(0), omega, kappa, fo);
+#pragma unroll
+          for (int i = 0; i < Q; ++i) out[i][c] = fo[i];
           if (REC) {
-            const long long g = dm.off + o_;
-            stv<M, M, CPL>(rec.n + g, recv[0]);
-            stv<M, M, CPL>(rec.j + g, recv[1]);
-            stv<M, M, CPL>(rec.j + rec.cells + g, recv[2]);
-            stv<M, M, CPL>(rec.F + g, recv[3]);
-            stv<M, M, CPL>(rec.F + rec.cells + g, recv[4]);
+            recv[0][c] = nn; recv[1][c] = jx; recv[2][c] = jy; recv[3][c] = Fx; recv[4][c] = Fy;
           }
         }
-      }
-    });
-  }
+        const uint32_t so_ = rowok ? xbo : OFF;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          stb<S, M, CPL, SCL_STORE_AUX>(mkrsrc(ob + (long long)i * cells + orow, (uint32_t)nx * sizeof(S)), so_, out[i]);
+        if (REC) {
+          const long long g = dm.off + orow;
+          const uint32_t sm = rowok ? xbm : OFF;
+          const uint32_t rb = (uint32_t)nx * sizeof(M);
+          stb<M, M, CPL>(mkrsrc(rec.n + g, rb), sm, recv[0]);
+          stb<M, M, CPL>(mkrsrc(rec.j + g, rb), sm, recv[1]);
+          stb<M, M, CPL>(mkrsrc(rec.j + rec.cells + g, rb), sm, recv[2]);
+          stb<M, M, CPL>(mkrsrc(rec.F + g, rb), sm, recv[3]);
+          stb<M, M, CPL>(mkrsrc(rec.F + rec.cells + g, rb), sm, recv[4]);
+        }
+      });
+    }
   };
   if (seam) march(std::true_type{});
   else march(std::false_type{});

@@ -1,11 +1,12 @@
-// Fused D3Q19 Shan-Chen step (2.5-D blocking): one workgroup owns a TX x TY tile of lanes
-// (its central (TX - 2R) x (TY - 2R) sites are outputs, the R-wide rim only supplies psi) and
-// marches along z. At every plane it pulls the 19 populations streaming into the tile,
-// stores psi(n) in a ring of 2R + 2 planes in LDS and collides the plane R behind, whose
-// populations wait in registers (rotation of R + 1 register sets). Same arithmetic as the
-// 2D kernel: force of eq. (sc_f) over +-pairs, eqs. (f_eq), (GuoForcing), (lbm), (omega_i).
+// D3Q19 Shan-Chen step in two passes: a density/psi pass over every site, then a fused
+// force + collision + streaming pass that reads psi from LDS-staged tiles. (A single fused
+// pass, as in 2D, would have to recompute psi on a rim around every tile and hold R + 1
+// planes of 19 populations per lane in registers; in 3D that costs more than the 4 + 4 bytes
+// per site of the psi array.)
 #pragma once
 #include "scl_common.hpp"
+
+
 
 namespace scl {
 
@@ -66,115 +67,181 @@ template <> struct Shells<3, 1> {
 static_assert(make_half3(0).n == 13, "3D reach-1 half list");
 static_assert(make_half3(1).n == 46, "3D reach-2 half list");
 
+// ------------------------------------------------------------------ pass 1: density and psi
+// psi(x) = psi(n(x)) with n(x) = sum_i f_i(x) = sum_i A_i[x - xi_i] (the populations streaming
+// into x). One lane per site of one x-row chunk of a domain; grid (x chunks, ny, nz).
+template <class S, class M, bool SHIFT>
+__global__ void __launch_bounds__(256)
+k_psi3d(const S* __restrict__ fin, M* __restrict__ psi, DomDev dm) {
+  using V = Vel<1>;
+  constexpr int Q = V::Q;
+  const int nx = dm.nx, ny = dm.ny, nz = dm.nz;
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= nx) return;
+  const int y = blockIdx.y, z = blockIdx.z;
+  const long long plane = (long long)nx * ny, cells = plane * nz;
+  const S* __restrict__ fb = fin + dm.off * Q;
+  const int xs[3] = {wrapi(x + 1, nx), x, wrapi(x - 1, nx)};  // [1 + cx]: x - cx
+  const long long ys[3] = {(long long)wrapi(y + 1, ny) * nx, (long long)y * nx, (long long)wrapi(y - 1, ny) * nx};
+  const long long zs[3] = {(long long)wrapi(z + 1, nz) * plane, (long long)z * plane, (long long)wrapi(z - 1, nz) * plane};
+  M sum = M(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    sum += static_cast<M>(fb[(long long)i * cells + zs[1 + V::cz(i)] + ys[1 + V::cy(i)] + xs[1 + V::cx(i)]]);
+  const M n = SHIFT ? M(dm.rho0) + sum : sum;
+  psi[dm.off + (long long)z * plane + (long long)y * nx + x] = psi_eval<M>(n, dm.psi_kind, M(dm.eps), M(dm.inv_eps));
+}
+
+// ------------------------------------------------------------------ pass 2: force, collide, stream
+// One workgroup owns a TX x TY tile of output sites (one lane each; TX a multiple of 64 keeps
+// every lane row of a wave on whole cache lines) and marches along a range of z. psi of the
+// tile and an R-wide rim is staged plane by plane from the psi array into a ring of 2R + 2
+// LDS planes; the force of eq. (sc_f) reads it there. The 19 populations of the plane being
+// collided are pulled straight into registers, one plane ahead. Collision: eqs. (f_eq),
+// (GuoForcing), (lbm), (omega_i), as in the 2D step. Every memory instruction is issued by
+// every lane at every step (accesses with nothing to do carry an offset past the buffer's
+// end), so that the compiler keeps the next plane's loads in flight.
 template <class S, class M, int SET, int TX, int TY, bool SHIFT>
 __global__ void __launch_bounds__(TX * TY)
-k_step3d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restrict__ doms,
-         const WorkItem* __restrict__ items) {
+k_step3d(const S* __restrict__ fin, S* __restrict__ fout, const M* __restrict__ psi,
+         const DomDev* __restrict__ doms, const WorkItem* __restrict__ items, int nitems) {
   using V = Vel<1>;
   using SH = Shells<3, SET>;
   constexpr int Q = V::Q;
   constexpr int R = SH::R;
   constexpr int RING = 2 * R + 2;
-  constexpr int NSLOT = R + 1;
   constexpr int NT = TX * TY;
+  constexpr int PX = TX + 2 * R, PY = TY + 2 * R;  // staged psi plane (tile + rim)
+  constexpr int PN = PX * PY;
+  constexpr int PL = (PN + NT - 1) / NT;            // psi values each lane stages per plane
+  constexpr uint32_t OFF = 0x80000000u;
 
-  __shared__ M psis[RING][NT];
+  __shared__ M ring[RING][PN];
 
-  const WorkItem it = items[blockIdx.x];
+  // XCD-aware mapping (as in the 2D step): XCD k takes the k-th contiguous eighth of the items.
+  const int per = (nitems + 7) >> 3;
+  const int item = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (item >= nitems) return;
+  const WorkItem it = items[item];
   const DomDev& dm = doms[it.dom];
   const int nx = dm.nx, ny = dm.ny, nz = dm.nz;
   const long long plane = (long long)nx * ny;
   const long long cells = plane * nz;
   const S* __restrict__ fb = fin + dm.off * Q;
   S* __restrict__ ob = fout + dm.off * Q;
-  const M omega = M(dm.omega), kappa = M(dm.kappa), gpre = M(dm.gpre);
-  const M eps = M(dm.eps), inv_eps = M(dm.inv_eps), rho0 = M(dm.rho0);
-  const int kind = dm.psi_kind;
+  const M* __restrict__ pb = psi + dm.off;
+  const M omega = M(dm.omega), kappa = M(dm.kappa), gpre = M(dm.gpre), rho0 = M(dm.rho0);
   M Wv[SH::NS];
 #pragma unroll
   for (int s = 0; s < SH::NS; ++s) Wv[s] = M(dm.W[s]);
 
   const int lane = threadIdx.x;
   const int tx = lane % TX, ty = lane / TX;
-  const int gx = it.x0 - R + tx, gy = it.y0 - R + ty;
-  const int xw = wrapi(gx, nx), xm = wrapi(gx - 1, nx), xp = wrapi(gx + 1, nx);
-  const int yw = wrapi(gy, ny), ym = wrapi(gy - 1, ny), yp = wrapi(gy + 1, ny);
-  const bool outl = tx >= R && tx < TX - R && ty >= R && ty < TY - R && gx < nx && gy < ny;
+  const int gx = it.x0 + tx, gy = it.y0 + ty;
+  const bool outl = gx < nx && gy < ny;
+  const uint32_t pbytes = (uint32_t)(plane * (long long)sizeof(S));
+  const uint32_t qbytes = (uint32_t)(plane * (long long)sizeof(M));
+  // pull offsets within a z-plane: po[1 - cy][1 - cx] = offset of (gx - cx, gy - cy)
+  uint32_t po[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      po[a][b] = outl ? (uint32_t)((long long)wrapi(gy + a - 1, ny) * nx + wrapi(gx + b - 1, nx)) * sizeof(S) : OFF;
+  const uint32_t oo = outl ? (uint32_t)((long long)gy * nx + gx) * sizeof(S) : OFF;
+  // psi staging: lane stages ring positions lane + NT * m of the (PX x PY) plane
+  uint32_t so[PL];
+#pragma unroll
+  for (int m = 0; m < PL; ++m) {
+    const int p = lane + NT * m;
+    const int px = p % PX, py = p / PX;
+    so[m] = p < PN ? (uint32_t)((long long)wrapi(it.y0 - R + py, ny) * nx + wrapi(it.x0 - R + px, nx)) * sizeof(M) : OFF;
+  }
 
-  const int total = (it.z1 - it.z0) + 2 * R;
-  M fr[NSLOT][Q];
+  const int dir = it.dir;
+  const int total = it.z1 - it.z0;  // planes collided
+  const int zstart = dir > 0 ? it.z0 : it.z1 - 1;
+  const int zbase = it.z0 - R - RING - 2;  // ring slot of plane z: (z - zbase) % RING
 
-  for (int k0 = 0; k0 < total; k0 += NSLOT) {
-    static_for<NSLOT>([&](auto J) {
+  M fr[2][Q];   // populations of the plane being collided and of the next one
+  M pv[2][PL];  // psi values being staged: plane z + R (in flight) and the next
+  auto load_pops = [&](int z, bool ok, M* dst) {
+    const long long zo[3] = {(long long)wrapi(z - 1, nz) * plane, (long long)wrapi(z, nz) * plane,
+                             (long long)wrapi(z + 1, nz) * plane};
+    const uint32_t sel = ok ? 0u : OFF;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      ldb<S, M, 1>(mkrsrc(fb + (long long)i * cells + zo[1 - V::cz(i)], pbytes), po[1 - V::cy(i)][1 - V::cx(i)] | sel, &dst[i]);
+  };
+  auto load_psi = [&](int z, M* dst) {
+    const Rsrc rs = mkrsrc(pb + (long long)wrapi(z, nz) * plane, qbytes);
+#pragma unroll
+    for (int m = 0; m < PL; ++m) ldb<M, M, 1>(rs, so[m], &dst[m]);
+  };
+  auto put_psi = [&](int z, const M* v) {
+    M* dst = ring[(z - zbase) % RING];
+#pragma unroll
+    for (int m = 0; m < PL; ++m)
+      if (lane + NT * m < PN) dst[lane + NT * m] = v[m];
+  };
+
+  // prologue: psi planes zstart - dir R .. zstart + dir (R - 1) into the ring
+  for (int d = -R; d < R; ++d) {
+    load_psi(zstart + dir * d, pv[0]);
+    put_psi(zstart + dir * d, pv[0]);
+  }
+  load_psi(zstart + dir * R, pv[0]);
+  load_pops(zstart, true, fr[0]);
+
+  for (int k0 = 0; k0 < total; k0 += 2) {
+    static_for<2>([&](auto J) {
       constexpr int j = decltype(J)::value;
       const int k = k0 + j;
-      if (k < total) {
-        const int zp_ = it.z0 - R + k;
-        const long long zw = (long long)wrapi(zp_, nz) * plane;
-        const long long zm = (long long)wrapi(zp_ - 1, nz) * plane;
-        const long long zpp = (long long)wrapi(zp_ + 1, nz) * plane;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          const int cx = V::cx(i), cy = V::cy(i), cz = V::cz(i);
-          const long long sz = cz == 1 ? zm : (cz == -1 ? zpp : zw);
-          const int sy = cy == 1 ? ym : (cy == -1 ? yp : yw);
-          const int sx = cx == 1 ? xm : (cx == -1 ? xp : xw);
-          fr[j][i] = ld<S, M>(fb + (long long)i * cells + sz + (long long)sy * nx + sx);
-        }
-        {
-          M sum = M(0);
-#pragma unroll
-          for (int i = 0; i < Q; ++i) sum += fr[j][i];
-          const M n = SHIFT ? rho0 + sum : sum;
-          psis[k % RING][lane] = psi_eval<M>(n, kind, eps, inv_eps);
-        }
-        __syncthreads();
+      const int z = zstart + dir * k;
+      // start the next plane's loads, then stage psi of plane z + R
+      load_psi(z + dir * (R + 1), pv[1 - j]);
+      load_pops(z + dir, k + 1 < total, fr[1 - j]);
+      put_psi(z + dir * R, pv[j]);
+      __syncthreads();
 
-        if (k >= 2 * R && outl) {
-          constexpr int js = (j + 1) % NSLOT;
-          const int c = zp_ - R;
-          int so[2 * R + 1];
+      int sl[2 * R + 1];  // ring slots of planes z + dz, dz = o - R
 #pragma unroll
-          for (int o = 0; o <= 2 * R; ++o) so[o] = (k - 2 * R + o) % RING;
-          const M psic = psis[so[R]][lane];
-          M dxs[SH::NS], dys[SH::NS], dzs[SH::NS];
+      for (int o = 0; o <= 2 * R; ++o) sl[o] = (z - R + o - zbase) % RING;
+      const int c0 = (ty + R) * PX + tx + R;  // this lane's site in a staged plane
+      M fo[Q];
+      const M psic = ring[sl[R]][c0];
+      M ax = M(0), ay = M(0), az = M(0);
+      // force of eq. (sc_f) over +-pairs, each difference weighted as it is read
 #pragma unroll
-          for (int s = 0; s < SH::NS; ++s) { dxs[s] = M(0); dys[s] = M(0); dzs[s] = M(0); }
-#pragma unroll
-          for (int h = 0; h < SH::NH; ++h) {
-            const HalfVec hv = SH::h(h);
-            const int dl = hv.y * TX + hv.x;
-            const M d = psis[so[R + hv.z]][lane + dl] - psis[so[R - hv.z]][lane - dl];
-            if (hv.x != 0) dxs[hv.slot] += M(hv.x) * d;
-            if (hv.y != 0) dys[hv.slot] += M(hv.y) * d;
-            if (hv.z != 0) dzs[hv.slot] += M(hv.z) * d;
-          }
-          M ax = M(0), ay = M(0), az = M(0);
-#pragma unroll
-          for (int s = 0; s < SH::NS; ++s) { ax += Wv[s] * dxs[s]; ay += Wv[s] * dys[s]; az += Wv[s] * dzs[s]; }
-          const M Fx = gpre * psic * ax, Fy = gpre * psic * ay, Fz = gpre * psic * az;
-
-          M sum = M(0), jx = M(0), jy = M(0), jz = M(0);
-#pragma unroll
-          for (int i = 0; i < Q; ++i) {
-            const M f = fr[js][i];
-            sum += f;
-            if (V::cx(i) != 0) jx += M(V::cx(i)) * f;
-            if (V::cy(i) != 0) jy += M(V::cy(i)) * f;
-            if (V::cz(i) != 0) jz += M(V::cz(i)) * f;
-          }
-          const M nn = SHIFT ? rho0 + sum : sum;
-          const M inv_n = rcp<M>(nn);
-          const M ux = (jx + M(0.5) * Fx) * inv_n;
-          const M uy = (jy + M(0.5) * Fy) * inv_n;
-          const M uz = (jz + M(0.5) * Fz) * inv_n;
-          const long long o = (long long)wrapi(c, nz) * plane + (long long)yw * nx + xw;
-          M fo[Q];
-          collide<1, M>(fr[js], SHIFT ? sum : nn, nn, ux, uy, uz, Fx, Fy, Fz, omega, kappa, fo);
-#pragma unroll
-          for (int i = 0; i < Q; ++i) st<S, M>(ob + (long long)i * cells + o, fo[i]);
-        }
+      for (int h = 0; h < SH::NH; ++h) {
+        const HalfVec hv = SH::h(h);
+        const int dl = hv.y * PX + hv.x;
+        const M wd = Wv[hv.slot] * (ring[sl[R + hv.z]][c0 + dl] - ring[sl[R - hv.z]][c0 - dl]);
+        if (hv.x != 0) ax += M(hv.x) * wd;
+        if (hv.y != 0) ay += M(hv.y) * wd;
+        if (hv.z != 0) az += M(hv.z) * wd;
       }
+      const M Fx = gpre * psic * ax, Fy = gpre * psic * ay, Fz = gpre * psic * az;
+      M sum = M(0), jx = M(0), jy = M(0), jz = M(0);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const M f = fr[j][i];
+        sum += f;
+        if (V::cx(i) != 0) jx += M(V::cx(i)) * f;
+        if (V::cy(i) != 0) jy += M(V::cy(i)) * f;
+        if (V::cz(i) != 0) jz += M(V::cz(i)) * f;
+      }
+      const M nn = SHIFT ? rho0 + sum : sum;
+      const M inv_n = rcp<M>(nn);
+      const M ux = (jx + M(0.5) * Fx) * inv_n;
+      const M uy = (jy + M(0.5) * Fy) * inv_n;
+      const M uz = (jz + M(0.5) * Fz) * inv_n;
+      collide<1, M>(fr[j], SHIFT ? sum : nn, nn, ux, uy, uz, Fx, Fy, Fz, omega, kappa, fo);
+      const long long cz = (long long)wrapi(z, nz) * plane;
+      const uint32_t sv = k < total ? oo : OFF;
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        stb<S, M, 1, SCL_STORE_AUX>(mkrsrc(ob + (long long)i * cells + cz, pbytes), sv, &fo[i]);
     });
   }
 }
