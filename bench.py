@@ -186,13 +186,17 @@ def main():
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
-    ap.add_argument("--mode", default="bench", choices=["bench", "copy"])
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "d3q19"],
+                    help="copy: device copy for counter calibration; d3q19: the 3D leg alone")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.mode == "copy":
         copy_calibration()
+        return
+    if args.mode == "d3q19":
+        print(json.dumps({"d3q19_512cube_fp32": d3q19_leg(None, steps=args.steps)}), flush=True)
         return
 
     import torch
@@ -236,6 +240,13 @@ def main():
             if prec == SCL_FP64:
                 n64 = lv.density()
                 var["fp32_shifted_vs_fp64_density_rel_err"] = float(np.abs(n_fp32 - n64).max() / np.abs(n64).max())
+                # the same FP64 run from n0 perturbed by 1e-15 (relative): how far the spinodal
+                # dynamics alone carries a rounding-level difference over the same steps
+                lt = make_lattice(SCL_FP64, W, G, n0 * (1.0 + 1e-15), stream)
+                lt.step(args.steps + args.warmup)
+                nt = lt.density()
+                var["fp64_twin_perturbed_1e-15_density_rel_err"] = float(np.abs(nt - n64).max() / np.abs(n64).max())
+                lt.close()
             lv.close()
         if not args.no_3d:
             var["d3q19_512cube_fp32"] = d3q19_leg(stream)
