@@ -87,6 +87,49 @@ def c5_targets(obs):
     return obs[:, 3] * (1 + 0.05 * u[:ndom]), obs[:, 5] + 0.5 * u[ndom:]
 
 
+def c3_workload():
+    """Batched Laplace-test workload: 32 radii R_k = 8 * 16^(k/31) (log-spaced 8..128), each
+    as a droplet (domain 2k) and a bubble (domain 2k + 1) in a periodic square of side
+    round(4 R_k + 32) (64..544; 3,976,466 sites in all). E(8) weights, psi = exp(-1/n),
+    G = 1.2 G_c, tau = 1, tanh profile of width 3 between the coexistence densities of
+    eq. (SCMaxwell) for the stencil's eps = 10/31, noise U(-1e-3, 1e-3) with seed 100 + domain.
+    Returns dims, n0 (concatenated), W, G, centers, is_bubble, radii."""
+    from paper_2505_23647_amd import synth, thermo
+    W = [4 / 21, 4 / 45, 1 / 60, 2 / 315, 1 / 5040]
+    G = thermo.coupling_for_reduced_temperature(0.2)
+    ng, nl = thermo.coexistence_exp(G, eps=thermo.epsilon(4 / 7))[:2]
+    radii = synth.log_radii(32, 8.0, 128.0)
+    dims, n0, centers, bubble = [], [], [], []
+    for k, R in enumerate(radii):
+        L = int(round(4 * R + 32))
+        for b in (0, 1):
+            dom = 2 * k + b
+            n_in, n_out = (ng, nl) if b else (nl, ng)
+            dims.append((L, L))
+            n0.append(synth.droplet((L, L), R, n_in, n_out, noise=1e-3, seed=100 + dom))
+            centers.append((L // 2, L // 2))
+            bubble.append(b)
+    return dims, np.concatenate(n0), W, G, np.array(centers), np.array(bubble, dtype=np.int8), radii
+
+
+def batched_leg(stream, steps=2000):
+    """The batched Laplace workload (64 domains, 3,976,466 sites) stepped in one launch per
+    step, replayed through HIP graphs of 100 steps: whole-batch MLUPS with launch overheads."""
+    from paper_2505_23647_amd import SCL_FP32_SHIFTED, Lattice
+    dims, n0, W, G, centers, bubble, radii = c3_workload()
+    lat = Lattice(dims, SCL_FP32_SHIFTED, stream=stream).set_physics(1.0, G).set_stencil([1, 2, 4, 5, 8], W)
+    lat.init_density(n0)
+    lat.set_graph_steps(100)
+    lat.step(200)
+    ms = lat.step_timed(steps)
+    ml = lat.cells * steps / (ms / 1e3) / 1e6
+    ach = 2 * 9 * 4 * lat.cells / (ms / 1e3 / steps) / 1e9
+    out = {"domains": len(dims), "sites": lat.cells, "steps": steps, "MLUPS": round(ml, 1),
+           "achieved_GBs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4), "tiling": list(lat.get_tiling())}
+    lat.close()
+    return out
+
+
 def adjoint_leg(stream):
     """Wall time of the checkpointed forward (with the observables) and of the backward
     (observables VJP + recompute + reverse steps) on the batched droplet workload, FP32;
@@ -250,6 +293,7 @@ def main():
             lv.close()
         if not args.no_3d:
             var["d3q19_512cube_fp32"] = d3q19_leg(stream)
+        var["batched_64_domains_fp32_shifted"] = batched_leg(stream)
         out["variants"] = var
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(stream)

@@ -153,10 +153,14 @@ scl_status scl_get_pressure_tensor(scl_lattice lat, double* out, int32_t is_devi
  *   Pbar = (Pxx + Pyy)/2, dP = Pbar(centre) - Pbar(corner (0,0));
  *   C_d = int_0^{L/2} r (Pbar(corner) - Pyy(centre + r e_x)) dr, trapezoid on sites, mean of
  *         the +x and -x half-lines;
- *   R_s = sqrt(2 C_d / dP), sigma_s = (-1)^b dP R_s (stationary point of sigma[R]);
- *   R_e from pi R_e^2 n(centre) + (L^2 - pi R_e^2) n(corner) = M.
+ *   R_s = sqrt(2 C_d / dP), sigma_s = dP R_s (stationary point of sigma[R]);
+ *   R_e from pi R_e^2 n(centre) + (L^2 - pi R_e^2) n(corner) = M;
+ *   delta = (-1)^b (R_e - R_s), the Tolman length measured from the liquid side.
+ * The inside pressure is the higher one for droplets and bubbles alike (dP, R_s, sigma_s > 0
+ * for both); the sign (-1)^b of a bubble is that of its curvature.
+ * R_s, sigma_s and delta are NaN while C_d / dP < 0 (an unrelaxed domain).
  * center: ndom x 2 ints (x, y); is_bubble: ndom bytes (b), may be NULL (droplets).
- * out: ndom x 6 doubles (dP, C_d, R_s, sigma_s, R_e, R_e - R_s). Host arrays. */
+ * out: ndom x 6 doubles (dP, C_d, R_s, sigma_s, R_e, delta). Host arrays. */
 scl_status scl_droplet_observables(scl_lattice lat, const int32_t* center, const int8_t* is_bubble,
                                    double* out);
 

@@ -325,9 +325,13 @@ static void ptensor2d_cell(const Geom& g, const Stencil& st, const int* codes, c
 //   sigma[R] = R^{1-d} int_0^{L/2} r^{d-1} (P_J(r;R) - P_T(r)) dr with P_T(r) = P^yy on the
 //   horizontal half-lines through the centre (trapezoid on sites, mean of +x and -x), i.e.
 //   sigma[R] = C_d / R^{d-1} + Delta P R / d with C_d = int r^{d-1}(Pbar(corner) - P_T(r)) dr.
-//   Its stationary point gives R_s = (d (d-1) C_d / Delta P)^{1/d}, sigma_s = (-1)^b Delta P R_s/(d-1).
+//   Its stationary point gives R_s = (d (d-1) C_d / Delta P)^{1/d}, sigma_s = Delta P R_s/(d-1).
+//   The pressure inside is the higher one for droplets and bubbles alike, so Delta P, R_s and
+//   sigma_s are positive for both; the bubble's sign (-1)^b belongs to its curvature (the
+//   Tolman fits plot both branches against the signed curvature (-1)^b / R).
 //   Equimolar radius: pi R_e^2 n_in + (L^2 - pi R_e^2) n_out = M.
-// out = (Delta P, C_d, R_s, sigma_s, R_e, R_e - R_s).
+//   Tolman length measured from the liquid side: delta = (-1)^b (R_e - R_s).
+// out = (Delta P, C_d, R_s, sigma_s, R_e, delta).
 template <class T>
 static void droplet_obs2d(const Geom& g, const Stencil& st, const int* codes, const T* W, const T& G,
                           const std::vector<T>& n, const std::vector<T>& psi, int cx, int cy, int bubble,
@@ -353,14 +357,14 @@ static void droplet_obs2d(const Geom& g, const Stencil& st, const int* codes, co
     Cd = Cd + 0.5 * sum;
   }
   const T Rs = sqrt(2.0 * Cd / dP);
-  const T sig = (bubble ? -1.0 : 1.0) * dP * Rs;
+  const T sig = dP * Rs;
   T M(0.0);
   for (long c = 0; c < g.N(); ++c) M = M + n[c];
   const T nin = n[g.idx(cx, cy, 0)];
   const T nout = n[0];
   const double PI = 3.14159265358979323846;
   const T Re = sqrt((M - (double)L * (double)L * nout) / (PI * (nin - nout)));
-  out[0] = dP; out[1] = Cd; out[2] = Rs; out[3] = sig; out[4] = Re; out[5] = Re - Rs;
+  out[0] = dP; out[1] = Cd; out[2] = Rs; out[3] = sig; out[4] = Re; out[5] = (bubble ? -1.0 : 1.0) * (Re - Rs);
 }
 
 }  // namespace orc

@@ -1,7 +1,7 @@
 """Differentiable droplet observables: torch.autograd.Function over the library's adjoint.
 
 forward(W, G): runs the checkpointed forward on the GPU and returns the droplet observables
-(dP, C_d, R_s, sigma_s, R_e, R_e - R_s) of every domain. backward: the observables' vector-
+(dP, C_d, R_s, sigma_s, R_e, delta) of every domain. backward: the observables' vector-
 Jacobian product (explicit dependence on W and G plus dL/dn of the final state), then the
 adjoint through the time loop. All the arithmetic runs in libscl; this file only marshals.
 """

@@ -903,13 +903,13 @@ scl_status scl_droplet_observables(scl_lattice L, const int32_t* center, const i
       Cd += 0.5 * sum;
     }
     const double Rs = std::sqrt(2.0 * Cd / dP);
-    const bool bub = is_bubble && is_bubble[k];
-    const double sig = (bub ? -1.0 : 1.0) * dP * Rs;
+    const double sgn = (is_bubble && is_bubble[k]) ? -1.0 : 1.0;
+    const double sig = dP * Rs;
     const double nin = n[(size_t)(o + (long long)cy * Ls + cx)];
     const double nout = n[(size_t)o];
     const double Re = std::sqrt((mass[k] - (double)Ls * Ls * nout) / (M_PI * (nin - nout)));
     double* r6 = out + (size_t)6 * k;
-    r6[0] = dP; r6[1] = Cd; r6[2] = Rs; r6[3] = sig; r6[4] = Re; r6[5] = Re - Rs;
+    r6[0] = dP; r6[1] = Cd; r6[2] = Rs; r6[3] = sig; r6[4] = Re; r6[5] = sgn * (Re - Rs);
   }
   return SCL_OK;
 }
@@ -1233,9 +1233,9 @@ scl_status scl_droplet_observables_vjp(scl_lattice L, const int32_t* center, con
     const double Re = std::sqrt(Nn / Dd);
     // backward through the closed forms
     const double* g = gobs + (size_t)6 * k;
-    const double gRs = g[2] + g[3] * sgn * dP - g[5];
-    const double gRe = g[4] + g[5];
-    const double gdP = g[0] + g[3] * sgn * Rs - gRs * Rs / (2.0 * dP);
+    const double gRs = g[2] + g[3] * dP - sgn * g[5];
+    const double gRe = g[4] + sgn * g[5];
+    const double gdP = g[0] + g[3] * Rs - gRs * Rs / (2.0 * dP);
     const double gCd = g[1] + gRs / (Rs * dP);
     const double gN = gRe / (2.0 * Re * Dd), gD = -gRe * Nn / (2.0 * Re * Dd * Dd);
     const double gM = gN, gno = -(double)Ls * Ls * gN - M_PI * gD, gnc = M_PI * gD;

@@ -31,8 +31,18 @@ def _pressure(n, G, e2):
     return n * CS2 + 0.5 * G * CS2 * e2 * np.exp(-2.0 / n)
 
 
-def coexistence_exp(G: float, e2: float = 1.0):
+def epsilon(e4: float, e2: float = 1.0) -> float:
+    """eq. (eps_moments): eps = (6 e4 - 2 e2) / (6 e4 + e2)."""
+    return (6.0 * e4 - 2.0 * e2) / (6.0 * e4 + e2)
+
+
+def coexistence_exp(G: float, e2: float = 1.0, eps: float = 0.0):
     """(n_gas, n_liquid, p0) for psi = exp(-1/n) at coupling G < G_c.
+
+    eps is the exponent of the measure psi' / psi^(1 + eps) of eq. (SCMaxwell) (eps(e4) of the
+    stencil, eq. (eps_moments)); with s = 1/n it is exp(eps s) ds. For eps = 0 the equal-area
+    integral has the closed form above; otherwise it is integrated numerically (composite
+    Simpson rule on s, whose integrand is smooth between the two bulk roots).
 
     For a trial p0 between the spinodal pressures the two outer roots of P(n) = p0 are found by
     bisection on the monotone gas and liquid branches; the equal-area residual
@@ -78,7 +88,12 @@ def coexistence_exp(G: float, e2: float = 1.0):
     def area(p0):
         ng, nl = branches(p0)
         sg, sl = 1.0 / ng, 1.0 / nl
-        return p0 * (sg - sl) - (F(sg) - F(sl))
+        if eps == 0.0:
+            return p0 * (sg - sl) - (F(sg) - F(sl))
+        s_ = np.linspace(sl, sg, 4001)
+        f = (p0 - CS2 / s_ - CS2 * a * np.exp(-2.0 * s_)) * np.exp(eps * s_)
+        h = (sg - sl) / 4000
+        return h / 3.0 * (f[0] + f[-1] + 4.0 * f[1:-1:2].sum() + 2.0 * f[2:-1:2].sum())
 
     p0 = bisect(area, max(p_min, 1e-300) * (1 + 1e-12), p_max * (1 - 1e-12))
     ng, nl = branches(p0)

@@ -18,3 +18,12 @@ def test_coexistence_matches_oracle(dT):
 
 def test_critical_coupling():
     assert thermo.critical_coupling_exp() == -math.e ** 2
+
+
+@pytest.mark.parametrize("e4", [4 / 7, 0.5, 0.65])
+def test_coexistence_with_stencil_measure_matches_oracle(e4):
+    """eq. (SCMaxwell) with the measure psi'/psi^(1+eps), eps = eps(e4) of eq. (eps_moments)."""
+    G = thermo.coupling_for_reduced_temperature(0.2)
+    ng, nl, p0 = thermo.coexistence_exp(G, eps=thermo.epsilon(e4))
+    og, ol, op = othermo.coexistence(G, e4=e4)
+    assert abs(ng - og) < 1e-9 and abs(nl - ol) < 1e-9 and abs(p0 - op) < 1e-11
