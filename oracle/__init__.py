@@ -80,7 +80,7 @@ class Sim:
     Populations are stored as ``f[Q, N]`` in the order given by :func:`velset`.
     """
 
-    def __init__(self, dims, tau, G, codes, W, psi_kind=PSI_EXP, psi_param=0.0):
+    def __init__(self, dims, tau, G, codes, W, psi_kind=PSI_EXP, psi_param=0.0, force_squared=0.0):
         dims = tuple(int(v) for v in dims)
         self.d = len(dims)
         self.nx, self.ny = dims[0], dims[1]
@@ -90,6 +90,7 @@ class Sim:
         self.codes = np.ascontiguousarray(codes, dtype=np.int32)
         self.W = np.ascontiguousarray(W, dtype=np.float64)
         self.kind, self.p = int(psi_kind), float(psi_param)
+        self.aF = float(force_squared)  # A of T = 2uF - (A/tau) FF (0: the paper's Guo forcing)
         self.xi, self.w = velset(self.d)
         self.Q = len(self.w)
         self.f = np.zeros((self.Q, self.N))
@@ -103,10 +104,10 @@ class Sim:
     def run(self, nsteps: int) -> int:
         """Advance ``nsteps``; returns 0, or 5 if the mass became non-finite."""
         L = lib()
-        L.orc_run.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double] * 2 + [ctypes.c_int, ctypes.c_double,
+        L.orc_run.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double] * 3 + [ctypes.c_int, ctypes.c_double,
                               ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long]
         self.f = np.ascontiguousarray(self.f)
-        return L.orc_run(self.d, self.nx, self.ny, self.nz, self.tau, self.G, self.kind, self.p,
+        return L.orc_run(self.d, self.nx, self.ny, self.nz, self.tau, self.aF, self.G, self.kind, self.p,
                          len(self.codes), self.codes.ctypes.data, self.W.ctypes.data, self.f.ctypes.data,
                          int(nsteps))
 
@@ -149,7 +150,7 @@ class Sim:
 
 
 def droplet_tangent_linear(dims, tau, G, codes, W, n0, nsteps, center, bubble=False,
-                           psi_kind=PSI_EXP, psi_param=0.0):
+                           psi_kind=PSI_EXP, psi_param=0.0, force_squared=0.0):
     """Forward-mode (dual-number) run of the plain step loop from f = w n0.
 
     Returns (obs[6], jac[6, nshells+1]) where jac holds d obs / d (W_0..W_{k-1}, G).
@@ -159,13 +160,13 @@ def droplet_tangent_linear(dims, tau, G, codes, W, n0, nsteps, center, bubble=Fa
     W = np.ascontiguousarray(W, dtype=np.float64)
     n0 = np.ascontiguousarray(np.asarray(n0, dtype=np.float64).reshape(-1))
     L = lib()
-    L.orc_droplet_tl2d.argtypes = [ctypes.c_int] * 2 + [ctypes.c_double] * 2 + [ctypes.c_int, ctypes.c_double,
+    L.orc_droplet_tl2d.argtypes = [ctypes.c_int] * 2 + [ctypes.c_double] * 3 + [ctypes.c_int, ctypes.c_double,
                                    ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_void_p, ctypes.c_void_p]
     obs = np.zeros(6)
     jac = np.zeros((6, len(codes) + 1))
-    rc = L.orc_droplet_tl2d(nx, ny, float(tau), float(G), int(psi_kind), float(psi_param), len(codes),
+    rc = L.orc_droplet_tl2d(nx, ny, float(tau), float(force_squared), float(G), int(psi_kind), float(psi_param), len(codes),
                             codes.ctypes.data, W.ctypes.data, n0.ctypes.data, int(nsteps), int(center[0]),
                             int(center[1]), int(bool(bubble)), obs.ctypes.data, jac.ctypes.data)
     if rc != 0:

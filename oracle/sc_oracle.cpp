@@ -230,11 +230,15 @@ static void macro_fields(const Geom& g, const VelSet& vs, const Stencil& st, con
 // For every x, from time-t values only:
 //   u = (j + F/2)/n                                                (shifted velocity)
 //   feq_i = w_i n [1 + xi.u/c^2 + (xi.u)^2/(2c^4) - u.u/(2c^2)]   (eq. f_eq)
-//   S_i = (1 - 1/(2 tau)) w_i [xi.F/c^2 + ((xi.u)(xi.F) - c^2 u.F)/c^4]   (eq. GuoForcing, T=2uF)
+//   T_ab = 2 u_a F_b - (A/tau) F_a F_b                             (rank-two tensor of eq. GuoForcing;
+//                                                                   A = 0: T = 2uF, the paper's
+//                                                                   choice; A != 0: the F^2 terms of
+//                                                                   the appendix on eps and e4)
+//   S_i = (1 - 1/(2 tau)) w_i [xi.F/c^2 + (xi_a xi_b - c^2 delta_ab) T_ab / (2 c^4)]   (eq. GuoForcing)
 //   f_i(x + xi_i, t+1) = f_i - (f_i - feq_i)/tau + S_i            (eqs. lbm, omega_i)
 template <class T>
 static void step(const Geom& g, const VelSet& vs, const Stencil& st, const T* W, const T& G, double tau,
-                 int kind, double p, const T* f, T* fo) {
+                 double aF, int kind, double p, const T* f, T* fo) {
   std::vector<T> n, j, psi, F;
   macro_fields(g, vs, st, W, G, kind, p, f, n, j, psi, F);
   const long N = g.N();
@@ -249,13 +253,18 @@ static void step(const Geom& g, const VelSet& vs, const Stencil& st, const T* W,
       u[k] = (j[3 * c + k] + 0.5 * Fc[k]) / n[c];
     }
     const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const T uF = u[0] * Fc[0] + u[1] * Fc[1] + u[2] * Fc[2];
+    T Tt[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) Tt[a][b] = 2.0 * u[a] * Fc[b] - (aF / tau) * Fc[a] * Fc[b];
     for (int i = 0; i < vs.Q; ++i) {
-      const double cx = vs.xi[i][0], cy = vs.xi[i][1], cz = vs.xi[i][2];
-      const T xu = u[0] * cx + u[1] * cy + u[2] * cz;
-      const T xF = Fc[0] * cx + Fc[1] * cy + Fc[2] * cz;
+      const double xi[3] = {(double)vs.xi[i][0], (double)vs.xi[i][1], (double)vs.xi[i][2]};
+      const T xu = u[0] * xi[0] + u[1] * xi[1] + u[2] * xi[2];
+      const T xF = Fc[0] * xi[0] + Fc[1] * xi[1] + Fc[2] * xi[2];
       const T feq = vs.w[i] * n[c] * (1.0 + xu / CS2 + xu * xu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
-      const T S = kappa * vs.w[i] * (xF / CS2 + (xu * xF - CS2 * uF) / (CS2 * CS2));
+      T H(0.0);
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) H = H + (xi[a] * xi[b] - (a == b ? CS2 : 0.0)) * Tt[a][b];
+      const T S = kappa * vs.w[i] * (xF / CS2 + H / (2.0 * CS2 * CS2));
       const T fi = f[(long)i * N + c];
       const T fstar = fi - (fi - feq) / tau + S;
       fo[(long)i * N + g.idx(x + vs.xi[i][0], y + vs.xi[i][1], z + vs.xi[i][2])] = fstar;
@@ -416,7 +425,7 @@ int orc_init(int d, int nx, int ny, int nz, const double* n0, double* f) {
 }
 
 // Advance f (Q x N, SoA, x fastest) by nsteps. Returns 0, -1 (bad shell), 5 (non-finite mass).
-int orc_run(int d, int nx, int ny, int nz, double tau, double G, int kind, double p, int nshells,
+int orc_run(int d, int nx, int ny, int nz, double tau, double aF, double G, int kind, double p, int nshells,
             const int* codes, const double* W, double* f, long nsteps) {
   VelSet vs = make_velset(d);
   Stencil st;
@@ -425,7 +434,7 @@ int orc_run(int d, int nx, int ny, int nz, double tau, double G, int kind, doubl
   const long N = g.N();
   std::vector<double> buf((size_t)vs.Q * N);
   for (long t = 0; t < nsteps; ++t) {
-    step<double>(g, vs, st, W, G, tau, kind, p, f, buf.data());
+    step<double>(g, vs, st, W, G, tau, aF, kind, p, f, buf.data());
     std::memcpy(f, buf.data(), sizeof(double) * buf.size());
   }
   double M = 0.0;
@@ -494,7 +503,7 @@ int orc_droplet_obs2d(int nx, int ny, double G, int kind, double p, int nshells,
 // Tangent-linear run (d = 2): starting from f_i = w_i n0, advance nsteps carrying derivatives
 // with respect to (W_0 .. W_{nshells-1}, G); returns the six droplet observables and their
 // Jacobian jac[6 x (nshells+1)], the FP64 reference gradient.
-int orc_droplet_tl2d(int nx, int ny, double tau, double G, int kind, double p, int nshells,
+int orc_droplet_tl2d(int nx, int ny, double tau, double aF, double G, int kind, double p, int nshells,
                      const int* codes, const double* W, const double* n0, long nsteps, int cx, int cy,
                      int bubble, double* obs, double* jac) {
   if (nshells + 1 > ND) return -3;
@@ -512,7 +521,7 @@ int orc_droplet_tl2d(int nx, int ny, double tau, double G, int kind, double p, i
   for (int i = 0; i < vs.Q; ++i)
     for (long c = 0; c < N; ++c) f[(long)i * N + c] = Dual(vs.w[i] * n0[c]);
   for (long t = 0; t < nsteps; ++t) {
-    step<Dual>(g, vs, st, Wd.data(), Gd, tau, kind, p, f.data(), fo.data());
+    step<Dual>(g, vs, st, Wd.data(), Gd, tau, aF, kind, p, f.data(), fo.data());
     std::swap(f, fo);
   }
   std::vector<Dual> n, j, psi, F;

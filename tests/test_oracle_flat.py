@@ -109,3 +109,40 @@ def test_flat_bulk_densities_do_not_depend_on_higher_moments():
     for nl, ng in res[1:]:
         assert abs(nl - res[0][0]) < 1e-13 * nl
         assert abs(ng - res[0][1]) < 1e-13 * ng
+
+
+def test_flat_tolman_tuning_with_reach4_stencil():
+    """Sec. Higher-order Tolman length tuning, flat interfaces: on the shells {1,2,4,5,8,9,18}
+    with psi_eps (eps = 14/29), e4 = 4/5, e6 = e4^(3/2), e8 = e4^2 as reference and delta_0
+    scaled by 1 + Delta_delta, the converged bulk densities do not move (machine precision, as
+    the paper reports), delta changes linearly with Delta_delta, sigma_0 at the 1e-3 level."""
+    from oracle import stencil_algebra as sa2
+    eps, e4 = 14 / 29, 0.8
+    G = thermo.G_for_reduced_temperature(0.1, kind=1, eps=eps)
+    ng, nl, _ = thermo.coexistence(G, kind=1, eps=eps)
+    s0, s1 = -e4 / 2, e4 ** 1.5 / 4
+    d0 = 1 / 12 + 95 * e4 / 432 + 7 * e4 ** 1.5 / 72 - 5 * e4 ** 2 / 144
+    codes = [1, 2, 4, 5, 8, 9, 18]
+    res = {}
+    for dd in (-0.2, 0.0, 0.2):
+        target = {"e2": 1, "e4": Fraction(e4).limit_denominator(10 ** 9),
+                  "e6": Fraction(e4 ** 1.5).limit_denominator(10 ** 12),
+                  "e8": Fraction((1 / 12 + 95 * e4 / 432 + 7 * e4 ** 1.5 / 72 - d0 * (1 + dd)) * 144 / 5).limit_denominator(10 ** 12),
+                  "I40": 0, "I60": 0, "I80": 0}
+        Wd = sa2.solve(2, codes, target)
+        W = [float(Wd[c]) for c in codes]
+        s = oracle.Sim((128, 1), 1.0, G, codes, W, oracle.PSI_EPS, eps).init_density(synth.slab(128, nl, ng, 32.0))
+        assert s.run(60000) == 0
+        n = s.fields()["n"]
+        P = s.pressure_tensor()
+        assert (P[0].max() - P[0].min()) < 1e-12 * abs(P[0].mean())
+        lo, hi = flat.halves(128)[0]
+        res[dd] = (n.max(), n.min(), flat.delta_zemzs(n, P[0], P[1], lo, hi, n.max(), n.min()),
+                   flat.sigma0(P[0], P[1], lo, hi))
+    for dd in (-0.2, 0.2):
+        assert abs(res[dd][0] - res[0.0][0]) < 1e-13 * res[0.0][0]
+        assert abs(res[dd][1] - res[0.0][1]) < 1e-13 * res[0.0][1]
+        assert abs(res[dd][3] / res[0.0][3] - 1) < 1e-2
+    d = {k: v[2] for k, v in res.items()}
+    assert abs((d[0.2] - d[0.0]) / (d[0.0] - d[-0.2]) - 1.0) < 0.01
+    assert 0.9 < (d[0.2] - d[-0.2]) / (0.4 * d[0.0]) < 1.3

@@ -325,6 +325,37 @@ def test_post_collision_moments_closed_form():
     assert f_before.shape == s.f.shape
 
 
+def test_force_squared_term_moments():
+    """Extended Guo tensor of the appendix on eps and e4, T_ab = 2 u_a F_b - (A/tau) F_a F_b,
+    inserted in eq. (GuoForcing): the Hermite term leaves mass and momentum untouched and adds
+    -(1 - 1/2tau)(A/tau) F F to the second moment of the post-collision populations."""
+    A, tau = 0.7, 0.8
+    G = thermo.G_for_reduced_temperature(0.2)
+    ng, nl, _ = thermo.coexistence(G)
+    n0 = synth.droplet((32, 32), 8.0, nl, ng, noise=1e-2, seed=0)
+    ref = oracle.Sim((32, 32), tau, G, [1, 2], [1 / 3, 1 / 12]).init_density(n0)
+    s = oracle.Sim((32, 32), tau, G, [1, 2], [1 / 3, 1 / 12], force_squared=A).init_density(n0)
+    ref.run(7)
+    s.f = ref.f.copy()
+    fl = s.fields()
+    ref.run(1)
+    s.run(1)
+    def unstream(sim):
+        out = np.empty_like(sim.f)
+        for i, (cx, cy, _) in enumerate(sim.xi):
+            out[i] = np.roll(sim.f[i].reshape(32, 32), shift=(-cy, -cx), axis=(0, 1)).reshape(-1)
+        return out
+    fa, fb = unstream(s), unstream(ref)
+    xi = s.xi[:, :2].astype(float)
+    F = fl["F"][:, :2]
+    assert np.abs(fa.sum(0) - fb.sum(0)).max() < 1e-14
+    assert np.abs(np.einsum("iN,ia->Na", fa - fb, xi)).max() < 1e-14
+    d2 = np.einsum("iN,ia,ib->Nab", fa - fb, xi, xi)
+    want = -(1 - 0.5 / tau) * (A / tau) * np.einsum("Na,Nb->Nab", F, F)
+    assert np.abs(d2 - want).max() < 1e-14
+    assert np.abs(want).max() > 1e-6
+
+
 def test_mass_and_momentum_conservation():
     """Sec. Lattice Boltzmann: the collision conserves mass and momentum; the Shan-Chen force
     sums to zero over a periodic domain, so the total physical momentum is conserved."""
