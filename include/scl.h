@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define SCL_ABI_VERSION 1
+#define SCL_ABI_VERSION 2
 
 typedef struct scl_lattice_s* scl_lattice;
 
@@ -100,8 +100,17 @@ scl_status scl_destroy(scl_lattice lat);
 scl_status scl_set_physics(scl_lattice lat, const double* tau, const double* G, scl_psi kind,
                            const double* psi_param);
 
+/* Optional F^2 part of the Guo tensor (appendix on the role of eps and e4): with A != 0 the
+ * rank-two tensor of eq. (GuoForcing) becomes T_ab = 2 u_a F_b - (A/tau) F_a F_b, which adds
+ * a forcing contribution eps_F to the interface-profile exponent. A: ndom doubles (host),
+ * finite; the default A = 0 is the paper's T = 2uF. Also used by the adjoint. */
+scl_status scl_set_force_squared(scl_lattice lat, const double* A);
+
 /* Forcing stencil (eq. sc_f): nshells distinct shell codes and the weights W(code) per
- * domain, W laid out ndom x nshells. Weights must be finite. */
+ * domain, W laid out ndom x nshells. Weights must be finite. A shell code is |e|^2 of its
+ * vectors (App. "Defining the stencil"). D2Q9 accepts 1, 2, 4, 5, 8, 9, 16, 18 (9: (3,0),
+ * 16: (4,0), 18: (3,3) groups; a stencil using 9, 16 or 18 reaches 4 sites and runs with
+ * 128- or 256-lane strips, one site per lane); D3Q19 accepts 1, 2, 3, 4, 5, 6, 8. */
 scl_status scl_set_stencil(scl_lattice lat, int32_t nshells, const int32_t* shell_codes, const double* W);
 
 /* Initial state f_i(x, 0) = w_i n0(x): the fluid at rest. n0 holds cells doubles (host, or
@@ -163,6 +172,21 @@ scl_status scl_get_pressure_tensor(scl_lattice lat, double* out, int32_t is_devi
  * out: ndom x 6 doubles (dP, C_d, R_s, sigma_s, R_e, delta). Host arrays. */
 scl_status scl_droplet_observables(scl_lattice lat, const int32_t* center, const int8_t* is_bubble,
                                    double* out);
+
+/* Flat-interface observables of each D2Q9 domain holding a slab that varies along x (two
+ * interfaces, one in each half [0, nx/2) and [nx/2, nx); profiles are means over the rows),
+ * in double, from the lattice pressure tensor (Sec. "Interface Physics", Sec. "Tolman
+ * Length"), per interface:
+ *   sigma_0 = sum_x (P_N - P_T) (eq. sigma0pnpt), P_N = Pxx, P_T = Pyy;
+ *   z_s = sum_x x (P_N - P_T) / sigma_0 (eq. ZSDef);
+ *   z_e: position of the sharp step between the bulk densities that holds the half's mass
+ *        (vanishing adsorbance), site x standing for the cell [x - 1/2, x + 1/2);
+ *   delta = z_e - z_s measured from the liquid towards the vapour (eq. zemzs);
+ *   delta_ads = Gamma(z_s) / (n_l - n_g) (eq. deltaads).
+ * bulk: ndom x 2 doubles (n_l, n_g) or NULL (then the row-mean profile's max and min).
+ * out: ndom x 2 x 5 doubles (sigma_0, z_s, z_e, delta, delta_ads) for the lower half, then
+ * the upper. nx must be even and >= 4. Host arrays. */
+scl_status scl_flat_observables(scl_lattice lat, const double* bulk, double* out);
 
 /* Tiling of the fused step.
  *   2D: strip = output lanes per workgroup (64, 128 or 256); seg = rows one workgroup marches

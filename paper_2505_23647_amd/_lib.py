@@ -54,6 +54,8 @@ SIGNATURES = {
     "scl_reduce_conserved": (_I32, [_P, _P, _P]),
     "scl_get_pressure_tensor": (_I32, [_P, _P, _I32]),
     "scl_droplet_observables": (_I32, [_P, _P, _P, _P]),
+    "scl_flat_observables": (_I32, [_P, _P, _P]),
+    "scl_set_force_squared": (_I32, [_P, _P]),
     "scl_set_tiling": (_I32, [_P, _I32, _I32, _I32]),
     "scl_get_tiling": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "scl_tune": (_I32, [_P, ctypes.c_char_p]),

@@ -17,14 +17,15 @@ class DropletProblem:
     """A batch of droplet (or bubble) domains run for a fixed number of steps.
 
     dims: list of square (L, L); n0: concatenated initial densities; centers: (ndom, 2);
-    codes: shell codes; tau: per-domain relaxation times; psi_kind / psi_param as in scl.h.
+    codes: shell codes; tau: per-domain relaxation times; psi_kind / psi_param as in scl.h;
+    force_squared: A of the F^2 part of the Guo tensor (per domain or scalar, default 0).
     equilibrate: if > 0, the first load() relaxes n0 for that many steps with the parameters
     it is given, and that state becomes the fixed initial state of every later run, so the
     differentiated window starts from a droplet at mechanical equilibrium.
     """
 
     def __init__(self, dims, n0, centers, codes, tau, nsteps, every, precision, is_bubble=None,
-                 psi_kind=0, psi_param=None, stream=None, equilibrate=0):
+                 psi_kind=0, psi_param=None, stream=None, equilibrate=0, force_squared=0.0):
         self.lat = Lattice(dims, precision, stream=stream)
         self.n0 = np.ascontiguousarray(n0, dtype=np.float64)
         self.centers = np.asarray(centers, dtype=np.int32)
@@ -34,12 +35,14 @@ class DropletProblem:
         self.is_bubble = is_bubble
         self.psi_kind, self.psi_param = psi_kind, psi_param
         self.equilibrate = int(equilibrate)
+        self.force_squared = force_squared
         self.f0 = None
 
     def load(self, W, G):
         """Set the parameters and the initial state of the differentiated window."""
         lat = self.lat
         lat.set_physics(self.tau, G, self.psi_kind, self.psi_param)
+        lat.set_force_squared(self.force_squared)
         lat.set_stencil(self.codes, W)
         lat.init_density(self.n0)
         if self.equilibrate > 0:

@@ -8,7 +8,8 @@
 //   moments of mu:  m0 = sum w_i mu_i, m1 = sum w_i mu_i xi, m2 = sum w_i mu_i xi xi
 //   V    = 3 m1 + 9 m2.u - 3 m0 u                     (sum mu_i w_i dP_i/du, P_i = f^eq_i/(w_i n))
 //   ubar = omega n V + kappa (9 m2.F - 3 m0 F)         dL/du
-//   Fbar = kappa V + ubar / (2n)                       dL/dF(y)
+//   Fbar = kappa V + ubar / (2n) - kappa aff (9 m2.F - 3 m0 F)   dL/dF(y) (the last term: the F^2
+//                                                                part of the Guo tensor, aff = A/tau)
 //   nbar_loc = omega (m0 + 3 m1.u + 4.5 u.m2.u - 1.5 u.u m0) - ubar.u / n
 //   jbar = ubar / n
 //   psibar(y) = Fbar(y).F(y)/psi(y) + G c^2 sum_a W_a psi(y + e_a) Fbar(y + e_a).e_a
@@ -74,7 +75,7 @@ __global__ void k_adj_get(const M* __restrict__ lam, double* __restrict__ out, l
   if (c < n) out[c] = static_cast<double>(lam[c]);
 }
 
-constexpr int ADJ_MAXS = 5;  // weight slots of the 2D reach-2 set
+constexpr int ADJ_MAXS = MAX_SHELLS;  // weight slots per domain
 
 template <class M, int SET, int NO>
 __global__ void __launch_bounds__((NO + 2 * Shells<2, SET>::R))
@@ -105,7 +106,7 @@ k_adjoint2d(const M* __restrict__ lin, M* __restrict__ lout, const M* __restrict
   const long long cells = (long long)nx * ny;
   const M* __restrict__ lb = lin + dm.off * Q;
   M* __restrict__ ob = lout + dm.off * Q;
-  const M omega = M(dm.omega), kappa = M(dm.kappa), gpre = M(dm.gpre);
+  const M omega = M(dm.omega), kappa = M(dm.kappa), gpre = M(dm.gpre), aff = M(dm.aff);
   const M eps = M(dm.eps), inv_eps = M(dm.inv_eps);
   const int kind = dm.psi_kind;
   M Wv[NS];
@@ -172,7 +173,8 @@ k_adjoint2d(const M* __restrict__ lin, M* __restrict__ lout, const M* __restrict
           const M Tx = M(9) * (mxx * Fx + mxy * Fy) - M(3) * m0 * Fx;
           const M Ty = M(9) * (mxy * Fx + myy * Fy) - M(3) * m0 * Fy;
           const M ubx = omega * n * Vx + kappa * Tx, uby = omega * n * Vy + kappa * Ty;
-          const M Fbx = kappa * Vx + M(0.5) * ubx * inv_n, Fby = kappa * Vy + M(0.5) * uby * inv_n;
+          const M Fbx = kappa * Vx + M(0.5) * ubx * inv_n - kappa * aff * Tx;
+          const M Fby = kappa * Vy + M(0.5) * uby * inv_n - kappa * aff * Ty;
           const M uu = ux * ux + uy * uy;
           const M An = omega * (m0 + M(3) * (m1x * ux + m1y * uy) + M(4.5) * (ux * m2ux + uy * m2uy) -
                                 M(1.5) * uu * m0);

@@ -47,10 +47,11 @@ size_t storage_bytes(scl_precision p) {
 }
 
 // Shell codes of the compile-time sets (index = weight slot).
-const int SET2[2][5] = {{1, 2, 0, 0, 0}, {1, 2, 4, 5, 8}};
-const int SET2N[2] = {2, 5};
-const int SET3[2][7] = {{1, 2, 3, 0, 0, 0, 0}, {1, 2, 3, 4, 5, 6, 8}};
-const int SET3N[2] = {3, 7};
+const int NSETS2 = 3, NSETS3 = 2, SETW = 8;  // sets per dimension, row width of the tables
+const int SET2[NSETS2][SETW] = {{1, 2}, {1, 2, 4, 5, 8}, {1, 2, 4, 5, 8, 9, 16, 18}};
+const int SET2N[NSETS2] = {2, 5, 8};
+const int SET3[NSETS3][SETW] = {{1, 2, 3}, {1, 2, 3, 4, 5, 6, 8}};
+const int SET3N[NSETS3] = {3, 7};
 
 // 3D tile shapes selectable through scl_set_tiling(strip = index).
 struct Tile3 { int tx, ty; };
@@ -74,6 +75,7 @@ struct scl_lattice_s {
   // physics
   bool have_physics = false, have_stencil = false, have_state = false;
   std::vector<double> tau, G, psi_param, rho0;
+  std::vector<double> aF;          // A of the F^2 part of the Guo tensor (0: the paper's T = 2uF)
   int psi_kind = 0;
   int set = 1;                     // compile-time shell set
   std::vector<int> user_codes;     // as given
@@ -121,12 +123,13 @@ std::vector<DomDev> host_doms(const scl_lattice_s* L) {
     d.eps = L->psi_param[k];
     d.inv_eps = L->psi_param[k] != 0.0 ? 1.0 / L->psi_param[k] : 0.0;
     d.rho0 = L->rho0[k];
+    d.aff = L->aF[k] / L->tau[k];
     for (int s = 0; s < MAX_SHELLS; ++s) d.W[s] = L->Wslot[(size_t)k * MAX_SHELLS + s];
   }
   return v;
 }
 
-int stencil_reach(const scl_lattice_s* L) { return L->set == 0 ? 1 : 2; }
+int stencil_reach(const scl_lattice_s* L) { return L->set == 0 ? 1 : (L->set == 1 ? 2 : 4); }
 
 // All forcing vectors (both of every pair) of the lattice's compile-time set.
 VecTable full_table(const scl_lattice_s* L) {
@@ -141,7 +144,9 @@ VecTable full_table(const scl_lattice_s* L) {
         t.v[t.n++] = HalfVec{(int8_t)-h.x, (int8_t)-h.y, (int8_t)-h.z, h.slot};
       }
     };
-    if (L->set == 0) add(Shells<2, 0>{}); else add(Shells<2, 1>{});
+    if (L->set == 0) add(Shells<2, 0>{});
+    else if (L->set == 1) add(Shells<2, 1>{});
+    else add(Shells<2, 2>{});
   } else {
     Half3Table h = make_half3(L->set);
     for (int k = 0; k < h.n; ++k) {
@@ -264,6 +269,7 @@ hipError_t launch2d(scl_lattice_s* L, const void* fin, void* fout, MacroRec<M> r
   SCL_2D_CASE(1, 64, 1) SCL_2D_CASE(1, 128, 1) SCL_2D_CASE(1, 256, 1)
   SCL_2D_CASE(0, 64, 2) SCL_2D_CASE(0, 128, 2) SCL_2D_CASE(0, 256, 2)
   SCL_2D_CASE(1, 64, 2) SCL_2D_CASE(1, 128, 2) SCL_2D_CASE(1, 256, 2)
+  SCL_2D_CASE(2, 128, 1) SCL_2D_CASE(2, 256, 1)
 #undef SCL_2D_CASE
   return hipErrorInvalidValue;
 }
@@ -558,6 +564,7 @@ scl_status scl_create(scl_velset vs, scl_precision prec, int32_t ndom, const int
   L->G.assign(ndom, 0.0);
   L->psi_param.assign(ndom, 0.0);
   L->rho0.assign(ndom, 0.0);
+  L->aF.assign(ndom, 0.0);
   L->Wslot.assign((size_t)ndom * MAX_SHELLS, 0.0);
   const size_t bytes = (size_t)L->Q * tot * storage_bytes(prec);
   if (hipMalloc(&L->A, bytes) != hipSuccess || hipMalloc(&L->B, bytes) != hipSuccess) {
@@ -615,30 +622,51 @@ scl_status scl_set_physics(scl_lattice L, const double* tau, const double* G, sc
   return SCL_OK;
 }
 
+scl_status scl_set_force_squared(scl_lattice L, const double* A) {
+  if (!L || !A) return fail(SCL_E_INVALID, "bad arguments");
+  for (int k = 0; k < L->ndom; ++k)
+    if (!std::isfinite(A[k])) return fail(SCL_E_INVALID, "A must be finite");
+  L->aF.assign(A, A + L->ndom);
+  L->dirty_doms = true;
+  drop_graph(L);
+  return SCL_OK;
+}
+
 scl_status scl_set_stencil(scl_lattice L, int32_t nshells, const int32_t* codes, const double* W) {
   if (!L || !codes || !W || nshells < 1 || nshells > MAX_SHELLS) return fail(SCL_E_INVALID, "bad stencil arguments");
   const int* sets = L->d == 2 ? &SET2[0][0] : &SET3[0][0];
-  const int width = L->d == 2 ? 5 : 7;
+  const int nsets = L->d == 2 ? NSETS2 : NSETS3;
   const int* setn = L->d == 2 ? SET2N : SET3N;
-  int set = 0;
   std::vector<int> slot(nshells, -1);
-  for (int s = 0; s < nshells; ++s) {
+  for (int s = 0; s < nshells; ++s)
     for (int q = 0; q < s; ++q)
       if (codes[q] == codes[s]) return fail(SCL_E_INVALID, "repeated shell code");
-    bool in0 = false, in1 = false;
-    for (int q = 0; q < setn[0]; ++q) in0 |= sets[q] == codes[s];
-    for (int q = 0; q < setn[1]; ++q) in1 |= sets[width + q] == codes[s];
-    if (!in1) return fail(SCL_E_INVALID, "unsupported shell code " + std::to_string(codes[s]) +
-                                              (L->d == 2 ? " (2D supports 1,2,4,5,8)" : " (3D supports 1,2,3,4,5,6,8)"));
-    if (!in0) set = 1;
+  // the smallest compile-time set holding every requested shell
+  int set = -1;
+  for (int c = 0; c < nsets && set < 0; ++c) {
+    bool all = true;
+    for (int s = 0; s < nshells; ++s) {
+      bool in = false;
+      for (int q = 0; q < setn[c]; ++q) in |= sets[c * SETW + q] == codes[s];
+      all &= in;
+    }
+    if (all) set = c;
   }
+  if (set < 0)
+    return fail(SCL_E_INVALID, std::string("unsupported shell codes") +
+                                   (L->d == 2 ? " (2D supports 1,2,4,5,8,9,16,18)" : " (3D supports 1,2,3,4,5,6,8)"));
   for (int k = 0; k < L->ndom; ++k)
     for (int s = 0; s < nshells; ++s)
       if (!std::isfinite(W[(size_t)k * nshells + s])) return fail(SCL_E_INVALID, "weights must be finite");
   for (int s = 0; s < nshells; ++s)
     for (int q = 0; q < setn[set]; ++q)
-      if (sets[set * width + q] == codes[s]) slot[s] = q;
+      if (sets[set * SETW + q] == codes[s]) slot[s] = q;
   L->set = set;
+  if (L->d == 2 && set == 2) {
+    // the reach-4 set is built for one site per lane and 128- or 256-lane strips
+    if (L->strip == 64) L->strip = 128;
+    L->cpl_req = 0;
+  }
   L->user_codes.assign(codes, codes + nshells);
   L->slot_of_user = slot;
   std::fill(L->Wslot.begin(), L->Wslot.end(), 0.0);
@@ -914,11 +942,65 @@ scl_status scl_droplet_observables(scl_lattice L, const int32_t* center, const i
   return SCL_OK;
 }
 
+scl_status scl_flat_observables(scl_lattice L, const double* bulk, double* out) {
+  if (!L || !out) return fail(SCL_E_INVALID, "bad arguments");
+  if (L->d != 2) return fail(SCL_E_UNSUPPORTED, "flat-interface observables are implemented for D2Q9 only");
+  for (int k = 0; k < L->ndom; ++k)
+    if (L->nx[k] < 4 || L->nx[k] % 2) return fail(SCL_E_INVALID, "flat-interface observables need an even nx >= 4");
+  std::vector<double> P((size_t)3 * L->cells);
+  scl_status s = scl_get_pressure_tensor(L, P.data(), 0);
+  if (s != SCL_OK) return s;
+  std::vector<double> n((size_t)L->cells);
+  HIPCHK(hipMemcpy(n.data(), L->d_n, n.size() * sizeof(double), hipMemcpyDeviceToHost));
+  const long long C = L->cells;
+  for (int k = 0; k < L->ndom; ++k) {
+    const int nx = L->nx[k], ny = L->ny[k];
+    const long long o = L->off[k];
+    // profiles along x: means over the rows
+    std::vector<double> nb(nx, 0.0), pn(nx, 0.0), pt(nx, 0.0);
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const size_t c = (size_t)(o + (long long)y * nx + x);
+        nb[x] += n[c] / ny;
+        pn[x] += P[c] / ny;
+        pt[x] += P[(size_t)C + c] / ny;
+      }
+    double nl = bulk ? bulk[2 * k] : 0.0, ng = bulk ? bulk[2 * k + 1] : 0.0;
+    if (!(nl > 0.0 && ng > 0.0)) {
+      nl = *std::max_element(nb.begin(), nb.end());
+      ng = *std::min_element(nb.begin(), nb.end());
+    }
+    for (int h = 0; h < 2; ++h) {
+      const int lo = h * nx / 2, hi = (h + 1) * nx / 2;
+      double sig = 0.0, mom = 0.0, mass = 0.0;
+      for (int x = lo; x < hi; ++x) {
+        sig += pn[x] - pt[x];
+        mom += x * (pn[x] - pt[x]);
+        mass += nb[x];
+      }
+      const double zs = mom / sig;
+      // sharp step between the bulks holding the same mass; sites are cells [x - 1/2, x + 1/2)
+      const bool liquid_low = nb[lo] > nb[hi - 1];
+      const double nlo = liquid_low ? nl : ng, nhi = liquid_low ? ng : nl;
+      const double a = lo - 0.5, b = hi - 0.5;
+      const double ze = (mass + nlo * a - nhi * b) / (nlo - nhi);
+      const double orient = liquid_low ? 1.0 : -1.0;
+      const double delta = orient * (ze - zs);
+      const double gam = mass - (nlo * (zs - a) + nhi * (b - zs));
+      double* r = out + (size_t)10 * k + 5 * h;
+      r[0] = sig; r[1] = zs; r[2] = ze; r[3] = delta; r[4] = gam / (nl - ng);
+    }
+  }
+  return SCL_OK;
+}
+
 scl_status scl_set_tiling(scl_lattice L, int32_t strip, int32_t seg, int32_t cpl) {
   if (!L || strip < 0 || seg < 0 || cpl < 0) return fail(SCL_E_INVALID, "bad tiling");
   if (L->d == 2) {
     if (strip != 0 && strip != 64 && strip != 128 && strip != 256) return fail(SCL_E_INVALID, "2D strip must be 64, 128 or 256");
     if (cpl > 2) return fail(SCL_E_INVALID, "sites per lane must be 1 or 2 (0 = automatic)");
+    if (L->set == 2 && (strip == 64 || cpl == 2))
+      return fail(SCL_E_UNSUPPORTED, "the reach-4 shell set runs with 128- or 256-lane strips, one site per lane");
     if (cpl == 2)
       for (int k = 0; k < L->ndom; ++k)
         if (L->nx[k] % 2) return fail(SCL_E_INVALID, "two sites per lane need even domain widths");
@@ -974,8 +1056,10 @@ scl_status scl_tune(scl_lattice L, const char* cache_path) {
   }
   std::vector<std::pair<int, int>> cands;
   if (L->d == 2) {
-    for (int st : {64, 128, 256})
+    for (int st : {64, 128, 256}) {
+      if (st == 64 && L->set == 2) continue;
       for (int sg : {8, 16, 32, 64, 128}) cands.push_back({st, sg});
+    }
   } else {
     for (int t : {1, 2, 3}) {
       for (int sg : {8, 16, 32, 64}) cands.push_back({t, sg});
@@ -1127,8 +1211,8 @@ scl_status scl_adjoint(scl_lattice L, const double* seed_n, const double* seed_f
   hipLaunchKernelGGL((k_adjoint2d<M_, SETV, NO>), dim3(8 * per), dim3(NO + 2 * Shells<2, SETV>::R), 0, L->stream, \
                      (const M_*)a.lam[cur], (M_*)a.lam[1 - cur], (const M_*)base, (const M_*)base + C,          \
                      (const M_*)base + 3 * C, C, L->d_doms, d_items, nitems, a.gpart, acc)
-      if (f64) { if (L->set == 0) ADJ_LAUNCH(double, 0); else ADJ_LAUNCH(double, 1); }
-      else { if (L->set == 0) ADJ_LAUNCH(float, 0); else ADJ_LAUNCH(float, 1); }
+      if (f64) { if (L->set == 0) ADJ_LAUNCH(double, 0); else if (L->set == 1) ADJ_LAUNCH(double, 1); else ADJ_LAUNCH(double, 2); }
+      else { if (L->set == 0) ADJ_LAUNCH(float, 0); else if (L->set == 1) ADJ_LAUNCH(float, 1); else ADJ_LAUNCH(float, 2); }
 #undef ADJ_LAUNCH
       HIPCHK(hipGetLastError());
       cur = 1 - cur;

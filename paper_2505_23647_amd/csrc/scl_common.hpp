@@ -67,6 +67,7 @@ template <> struct Vel<1> {
 //   2D set 1: {1,2,4,5,8}       (24 vectors, reach 2)
 //   3D set 0: {1,2,3}           (26 vectors, reach 1)
 //   3D set 1: {1,2,3,4,5,6,8}   (92 vectors, reach 2)
+// (2D set 2 follows the two below.)
 struct HalfVec { int8_t x, y, z, slot; };
 
 template <int D, int SET> struct Shells;
@@ -91,6 +92,23 @@ template <> struct Shells<2, 1> {
   }
 };
 
+//   2D set 2: {1,2,4,5,8,9,16,18} (36 vectors, reach 4; the shells of the paper's
+//             surface-tension and Tolman-length tuning stencils)
+template <> struct Shells<2, 2> {
+  static constexpr int R = 4, NH = 18, NS = 8;
+  __host__ __device__ static constexpr int code(int s) {
+    constexpr int c[8] = {1, 2, 4, 5, 8, 9, 16, 18};
+    return c[s];
+  }
+  __host__ __device__ static constexpr HalfVec h(int k) {
+    constexpr HalfVec v[18] = {{1, 0, 0, 0},  {0, 1, 0, 0},  {1, 1, 0, 1},  {-1, 1, 0, 1}, {2, 0, 0, 2},
+                               {0, 2, 0, 2},  {2, 1, 0, 3},  {1, 2, 0, 3},  {-1, 2, 0, 3}, {-2, 1, 0, 3},
+                               {2, 2, 0, 4},  {-2, 2, 0, 4}, {3, 0, 0, 5},  {0, 3, 0, 5},  {4, 0, 0, 6},
+                               {0, 4, 0, 6},  {3, 3, 0, 7},  {-3, 3, 0, 7}};
+    return v[k];
+  }
+};
+
 // 3D half lists are generated on the host into constant tables of this size.
 constexpr int MAX_HALF_3D = 46;
 
@@ -105,6 +123,7 @@ struct DomDev {
   double eps;           // pseudopotential parameter
   double inv_eps;       // 1 / eps
   double rho0;          // storage shift (0 when not shifted)
+  double aff;           // A / tau of the F^2 part of the Guo tensor, T = 2 u F - (A/tau) F F
   double W[MAX_SHELLS]; // weight of each shell slot of the compile-time set
 };
 
@@ -191,7 +210,10 @@ template <int VS> __host__ __device__ constexpr int opp(int i) {
 // ------------------------------------------------------------------ BGK + Guo collision
 // f*_i = f_i - omega (f_i - f_i^eq) + S_i  (eqs. lbm, omega_i) with
 //   f_i^eq = w_i n [1 + xi.u/c^2 + (xi.u)^2/(2c^4) - u.u/(2c^2)]          (eq. f_eq)
-//   S_i    = kappa w_i [xi.F/c^2 + ((xi.u)(xi.F) - c^2 u.F)/c^4]          (eq. GuoForcing, T = 2uF)
+//   S_i    = kappa w_i [xi.F/c^2 + (xi xi - c^2 1) : T / (2 c^4)]           (eq. GuoForcing)
+//            with T = 2 u F - aff F F: the paper's T = 2uF plus, for aff = A/tau != 0, the F^2
+//            terms of the appendix on eps and e4; the contraction is
+//            ((xi.u)(xi.F) - c^2 u.F)/c^4 - aff ((xi.F)^2 - c^2 F.F)/(2 c^4)
 // written as f*_i = (1 - omega) f_i + A +- B for each pair (i, opposite of i): A collects the
 // terms even in xi, B the odd ones. base = n for plain storage; for shifted storage (f holds
 // f - w rho0) base = n - rho0 = sum of the stored values, which subtracts w rho0 from f^eq.
@@ -199,11 +221,12 @@ template <int VS> __host__ __device__ constexpr int opp(int i) {
 // at once instead of holding all Q.
 template <int VS, class M, class Emit>
 __device__ __forceinline__ void collide_emit(const M* f, M base, M nn, M ux, M uy, M uz, M Fx, M Fy, M Fz,
-                                             M omega, M kappa, Emit&& emit) {
+                                             M omega, M kappa, M aff, Emit&& emit) {
   using V = Vel<VS>;
   constexpr int Q = V::Q;
   const M uu15 = M(1.5) * (ux * ux + uy * uy + uz * uz);  // u.u / (2 c^2)
-  const M uF3 = M(3) * (ux * Fx + uy * Fy + uz * Fz);     // c^2 u.F / c^4
+  const M uF3 = M(3) * (ux * Fx + uy * Fy + uz * Fz) - M(1.5) * aff * (Fx * Fx + Fy * Fy + Fz * Fz);
+  const M aff45 = M(4.5) * aff;
   const M om1 = M(1) - omega;
   const M on = omega * nn;
   const M obase = omega * base;
@@ -222,7 +245,7 @@ __device__ __forceinline__ void collide_emit(const M* f, M base, M nn, M ux, M u
       if constexpr (cy != 0) { xu += M(cy) * uy; xF += M(cy) * Fy; }
       if constexpr (cz != 0) { xu += M(cz) * uz; xF += M(cz) * Fz; }
       const M E = M(4.5) * xu * xu - uu15;
-      const M Se = M(9) * xu * xF - uF3;
+      const M Se = M(9) * xu * xF - aff45 * xF * xF - uF3;
       const M A = w * (obase + on * E) + (kappa * w) * Se;
       const M B = (M(3) * w) * (on * xu + kappa * xF);
       emit(i, om1 * f[i] + (A + B));
@@ -233,8 +256,8 @@ __device__ __forceinline__ void collide_emit(const M* f, M base, M nn, M ux, M u
 
 template <int VS, class M>
 __device__ __forceinline__ void collide(const M* f, M base, M nn, M ux, M uy, M uz, M Fx, M Fy, M Fz, M omega,
-                                        M kappa, M* fo) {
-  collide_emit<VS, M>(f, base, nn, ux, uy, uz, Fx, Fy, Fz, omega, kappa, [&](int i, M v) { fo[i] = v; });
+                                        M kappa, M aff, M* fo) {
+  collide_emit<VS, M>(f, base, nn, ux, uy, uz, Fx, Fy, Fz, omega, kappa, aff, [&](int i, M v) { fo[i] = v; });
 }
 
 // ------------------------------------------------------------------ buffer access

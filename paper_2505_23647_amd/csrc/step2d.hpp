@@ -114,7 +114,7 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
   const long long cells = (long long)nx * ny;
   const S* __restrict__ fb = fin + dm.off * Q;
   S* __restrict__ ob = fout + dm.off * Q;
-  const M omega = M(dm.omega), kappa = M(dm.kappa), gpre = M(dm.gpre);
+  const M omega = M(dm.omega), kappa = M(dm.kappa), gpre = M(dm.gpre), aff = M(dm.aff);
   const M eps = M(dm.eps), inv_eps = M(dm.inv_eps), rho0 = M(dm.rho0);
   const int kind = dm.psi_kind;
   M Wv[SH::NS];
@@ -257,7 +257,7 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
           const M ux = (jx + M(0.5) * Fx) * inv_n;
           const M uy = (jy + M(0.5) * Fy) * inv_n;
           M fo[Q];
-          collide<0, M>(f, SHIFT ? sum : nn, nn, ux, uy, M(0), Fx, Fy, M(0), omega, kappa, fo);
+          collide<0, M>(f, SHIFT ? sum : nn, nn, ux, uy, M(0), Fx, Fy, M(0), omega, kappa, aff, fo);
 #pragma unroll
           for (int i = 0; i < Q; ++i) out[i][c] = fo[i];
           if (REC) {

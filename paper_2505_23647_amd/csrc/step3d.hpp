@@ -131,6 +131,7 @@ k_step3d(const S* __restrict__ fin, S* __restrict__ fout, const M* __restrict__ 
   S* __restrict__ ob = fout + dm.off * Q;
   const M* __restrict__ pb = psi + dm.off;
   const M omega = M(dm.omega), kappa = M(dm.kappa), gpre = M(dm.gpre), rho0 = M(dm.rho0);
+  const M aff = M(dm.aff);
   M Wv[SH::NS];
 #pragma unroll
   for (int s = 0; s < SH::NS; ++s) Wv[s] = M(dm.W[s]);
@@ -236,7 +237,7 @@ k_step3d(const S* __restrict__ fin, S* __restrict__ fout, const M* __restrict__ 
       const M ux = (jx + M(0.5) * Fx) * inv_n;
       const M uy = (jy + M(0.5) * Fy) * inv_n;
       const M uz = (jz + M(0.5) * Fz) * inv_n;
-      collide<1, M>(fr[j], SHIFT ? sum : nn, nn, ux, uy, uz, Fx, Fy, Fz, omega, kappa, fo);
+      collide<1, M>(fr[j], SHIFT ? sum : nn, nn, ux, uy, uz, Fx, Fy, Fz, omega, kappa, aff, fo);
       const long long cz = (long long)wrapi(z, nz) * plane;
       const uint32_t sv = k < total ? oo : OFF;
 #pragma unroll

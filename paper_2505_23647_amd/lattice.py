@@ -79,6 +79,12 @@ class Lattice:
         check(lib().scl_set_physics(self.h, _dptr(tau), _dptr(G), psi_kind, _dptr(pp) if pp is not None else None))
         return self
 
+    def set_force_squared(self, A):
+        """A per domain (scalar broadcast) of T = 2uF - (A/tau) FF in the Guo term (default 0)."""
+        A = np.ascontiguousarray(np.broadcast_to(np.asarray(A, dtype=np.float64), (self.ndom,)))
+        check(lib().scl_set_force_squared(self.h, _dptr(A)))
+        return self
+
     def set_stencil(self, codes, W):
         codes = np.ascontiguousarray(codes, dtype=np.int32)
         W = np.asarray(W, dtype=np.float64)
@@ -177,6 +183,16 @@ class Lattice:
             b = np.ascontiguousarray(np.asarray(is_bubble, dtype=np.int8).reshape(self.ndom))
         out = np.empty((self.ndom, 6))
         check(lib().scl_droplet_observables(self.h, _dptr(c), _dptr(b) if b is not None else None, _dptr(out)))
+        return out
+
+    def flat_observables(self, bulk=None):
+        """[ndom, 2, 5]: (sigma_0, z_s, z_e, delta, delta_ads) of the lower and upper interface
+        of a slab varying along x; bulk: [ndom, 2] (n_l, n_g) or None."""
+        b = None
+        if bulk is not None:
+            b = np.ascontiguousarray(np.asarray(bulk, dtype=np.float64).reshape(self.ndom, 2))
+        out = np.empty((self.ndom, 2, 5))
+        check(lib().scl_flat_observables(self.h, _dptr(b) if b is not None else None, _dptr(out)))
         return out
 
     # ------------------------------------------------------------------ adjoint

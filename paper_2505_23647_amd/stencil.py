@@ -61,3 +61,75 @@ def seeded_family3d(u_e4: float, u_e8: float, u_w6: float):
     e8 = 16 / 105 * (1 + 0.1 * (2 * u_e8 - 1))
     w6 = 1 / 630 * (0.8 + 0.4 * u_w6)
     return e4, e8, w6, family3d(e4, e8, w6)
+
+
+# ---------------------------------------------------------------------- knob -> weight solver
+# The moments of a weighted stencil are linear in the weights, so fixing as many of them as
+# there are shells gives the weights by one linear solve (Sec. "Computing the Weights"). The
+# 2D moment names follow the definitions of the isotropy and anisotropy coefficients:
+#   e2 = <x^2>, e4 = <x^2 y^2>, e6 = <x^4 y^2>/3, e8 = <x^4 y^4>/9,
+#   I40 = <x^4> - 3 <x^2 y^2>, I60 = <x^6> - 15 e6, I80 = <x^6 y^2> - 15 e8,
+#   I81 = <x^8> - 7 <x^6 y^2>,
+# where <x^a y^b> = sum over stencil vectors of W(|e|^2) e_x^a e_y^b.
+
+TOLMAN_SHELLS_2D = (1, 2, 4, 5, 8, 9, 18)
+
+
+def shell_vectors_2d(code: int):
+    """All integer (x, y) with x^2 + y^2 = code."""
+    r = int(np.ceil(np.sqrt(code)))
+    return [(x, y) for x in range(-r, r + 1) for y in range(-r, r + 1) if x * x + y * y == code]
+
+
+def _moment_rows_2d(codes):
+    def m(a, b):
+        return np.array([sum(float(x) ** a * float(y) ** b for x, y in shell_vectors_2d(c)) for c in codes])
+
+    e6 = m(4, 2) / 3
+    e8 = m(4, 4) / 9
+    return {"e2": m(2, 0), "e4": m(2, 2), "e6": e6, "e8": e8,
+            "I40": m(4, 0) - 3 * m(2, 2), "I60": m(6, 0) - 15 * e6,
+            "I80": m(6, 2) - 15 * e8, "I81": m(8, 0) - 7 * m(6, 2)}
+
+
+def moments2d(codes, W):
+    """Named moments of a 2D stencil with weights W (one per shell code)."""
+    rows = _moment_rows_2d(codes)
+    return {k: float(v @ np.asarray(W, dtype=np.float64)) for k, v in rows.items()}
+
+
+def solve_weights_2d(codes, targets: dict) -> np.ndarray:
+    """Weights of the shells ``codes`` whose named moments take the values ``targets``
+    (exactly as many targets as shells)."""
+    if len(targets) != len(codes):
+        raise ValueError("need one target per shell")
+    rows = _moment_rows_2d(codes)
+    A = np.array([rows[k] for k in targets])
+    b = np.array([float(v) for v in targets.values()])
+    return np.linalg.solve(A, b)
+
+
+def moments_for_knobs(sigma0: float, sigma1: float, delta0: float):
+    """(e4, e6, e8) from the interface knobs: sigma_0 = -e4/2, sigma_1 = e6/4
+    (eq. hatsigma01eI) and delta_0 = 1/12 + 95 e4/432 + 7 e6/72 - 5 e8/144 (eq. hatdelta0eI)."""
+    e4 = -2.0 * sigma0
+    e6 = 4.0 * sigma1
+    e8 = (1.0 / 12 + 95.0 * e4 / 432 + 7.0 * e6 / 72 - delta0) * 144.0 / 5.0
+    return e4, e6, e8
+
+
+def tolman_stencil_2d(sigma0: float, sigma1: float, delta0: float) -> np.ndarray:
+    """Weights on the shells {1,2,4,5,8,9,18} with e2 = 1, sixth-order isotropy (I40 = I60 = 0),
+    I80 = 0 and the three knobs (sigma_0, sigma_1, delta_0): the stencil of the paper's
+    Tolman-length tuning (Sec. "Higher-order Tolman length tuning")."""
+    e4, e6, e8 = moments_for_knobs(sigma0, sigma1, delta0)
+    return solve_weights_2d(TOLMAN_SHELLS_2D, {"e2": 1.0, "e4": e4, "e6": e6, "e8": e8,
+                                               "I40": 0.0, "I60": 0.0, "I80": 0.0})
+
+
+def surface_tension_stencil_2d(sigma0: float, sigma1: float) -> np.ndarray:
+    """Weights on the shells {1,2,4,5,8,9,18} with e2 = 1, e4 = -2 sigma_0, e6 = 4 sigma_1 and
+    eighth-order isotropy (I40 = I60 = I80 = I81 = 0): the stencil of the paper's higher-order
+    surface-tension tuning (Sec. "Higher-order surface tension tuning")."""
+    return solve_weights_2d(TOLMAN_SHELLS_2D, {"e2": 1.0, "e4": -2.0 * sigma0, "e6": 4.0 * sigma1,
+                                               "I40": 0.0, "I60": 0.0, "I80": 0.0, "I81": 0.0})

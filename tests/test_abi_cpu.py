@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported_and_bound():
 
 
 def test_abi_version():
-    assert B.lib().scl_abi_version() == 1
+    assert B.lib().scl_abi_version() == 2
 
 
 def test_velocity_sets_match_oracle_sets():

@@ -27,10 +27,12 @@ def droplet_batch(sides, radii, seed0=0):
     return G, n0s, centers
 
 
-def test_gradient_matches_oracle_tangent_linear():
+@pytest.mark.parametrize("A", [0.0, 0.6])
+def test_gradient_matches_oracle_tangent_linear(A):
     """FP64: d(loss)/d(W, G) from the GPU adjoint equals the oracle's forward-mode Jacobian
-    contracted with the same dL/dobs (loss weights on sigma_s and delta), per domain."""
-    say("case: adjoint vs oracle tangent-linear")
+    contracted with the same dL/dobs (loss weights on sigma_s and delta), per domain; with the
+    paper's Guo tensor (A = 0) and with its F^2 part (A = 0.6)."""
+    say(f"case: adjoint vs oracle tangent-linear, A = {A}")
     # sizes and step counts where the droplets have stopped ringing (Delta P > 0, C_d > 0)
     sides, radii = [36, 40], [9.0, 10.0]
     G, n0s, centers = droplet_batch(sides, radii)
@@ -38,17 +40,20 @@ def test_gradient_matches_oracle_tangent_linear():
     steps, every = 800, 45
     gobs_all, ref_grads = [], []
     for k, L in enumerate(sides):
-        obs, jac = oracle.droplet_tangent_linear((L, L), 1.0, G, CODES, Ws[k], n0s[k], steps, centers[k])
+        obs, jac = oracle.droplet_tangent_linear((L, L), 1.0, G, CODES, Ws[k], n0s[k], steps, centers[k],
+                                                 force_squared=A)
         assert np.all(np.isfinite(obs)) and obs[0] > 0 and obs[1] > 0
         gobs = np.zeros(6)
         gobs[3] = 2 * (obs[3] - 1.05 * obs[3])
         gobs[5] = 2 * (obs[5] - (obs[5] + 0.5))
         gobs_all.append(gobs)
         ref_grads.append(gobs @ jac)
-    prob = DropletProblem([(L, L) for L in sides], np.concatenate(n0s), centers, CODES, 1.0, steps, every, SCL_FP64)
+    prob = DropletProblem([(L, L) for L in sides], np.concatenate(n0s), centers, CODES, 1.0, steps, every, SCL_FP64,
+                          force_squared=A)
     obs_gpu = prob.run(np.array(Ws), np.full(2, G))
     for k, L in enumerate(sides):
-        o_ref, _ = oracle.droplet_tangent_linear((L, L), 1.0, G, CODES, Ws[k], n0s[k], steps, centers[k])
+        o_ref, _ = oracle.droplet_tangent_linear((L, L), 1.0, G, CODES, Ws[k], n0s[k], steps, centers[k],
+                                                 force_squared=A)
         assert np.allclose(obs_gpu[k], o_ref, rtol=1e-10, atol=1e-12), k
     gW, gG = prob.vjp(np.array(gobs_all))
     for k in range(2):

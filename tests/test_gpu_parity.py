@@ -10,6 +10,7 @@ from paper_2505_23647_amd import (SCL_FP16S_FP32, SCL_FP32, SCL_FP32_SHIFTED, SC
 from paper_2505_23647_amd import _lib as B
 from tests.gpu_helpers import (E4_2D, E8_2D, coupling, family2d_weights, family3d_weights, oracle_run,
                                patch_oracle, perm_to_oracle, rel_err, say)
+import oracle
 from oracle import thermo
 
 pytestmark = pytest.mark.gpu
@@ -132,6 +133,28 @@ def test_batched_domains_fp64_and_fp32_bitwise():
     for k, d in enumerate(dims):
         one = gpu_run([d], SCL_FP32, 1.0, G, E8_2D[0], W[k], n0s[k], 120, tiling=(128, 24))
         assert np.array_equal(bat.domain_populations(k), one.domain_populations(0)), k
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_force_squared_term_fp64(d):
+    """The F^2 part of the Guo tensor, T = 2uF - (A/tau) FF (appendix on eps and e4): FP64
+    parity with the oracle in 2D (24-vector stencil) and 3D (92 vectors), tau != 1."""
+    say(f"case: F^2 forcing A = 0.6, d = {d}")
+    G = coupling(0.2)
+    if d == 2:
+        dims, codes, W = (150, 70), E8_2D[0], family2d_weights(0.55, 0.12)
+    else:
+        dims, codes, W = (40, 24, 20), [1, 2, 3, 4, 5, 6, 8], family3d_weights(4 / 7, 16 / 105, 1 / 630)
+    n0 = synth.uniform(dims, 0.8, 1.2, seed=31)
+    lat = Lattice([dims], SCL_FP64).set_physics(0.8, G).set_force_squared(0.6).set_stencil(codes, W)
+    lat.init_density(n0).step(60)
+    ora = oracle.Sim(dims, 0.8, G, codes, W, force_squared=0.6).init_density(n0)
+    assert ora.run(60) == 0
+    assert compare_domain(lat, 0, ora, FP64_TOL) <= FP64_TOL
+    # and the term matters: without it the states differ
+    ref = oracle.Sim(dims, 0.8, G, codes, W).init_density(n0)
+    ref.run(60)
+    assert rel_err(ref.f, ora.f) > 1e-8
 
 
 def test_fp32_error_bound_per_1000_steps():
