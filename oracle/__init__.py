@@ -136,6 +136,31 @@ class Sim:
         assert rc == 0
         return out
 
+    def pressure_tensor_general(self):
+        """Lattice pressure tensor by the link-sharing rule, d = 2 or 3: [6, N] planes
+        (xx, yy, zz, xy, xz, yz)."""
+        L = lib()
+        L.orc_ptensor.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_int] + [ctypes.c_void_p] * 4
+        out = np.zeros((6, self.N))
+        rc = L.orc_ptensor(self.d, self.nx, self.ny, self.nz, self.G, self.kind, self.p, len(self.codes),
+                           self.codes.ctypes.data, self.W.ctypes.data, self.f.ctypes.data, out.ctypes.data)
+        assert rc == 0
+        return out
+
+    def droplet_observables3d(self, center, bubble=False):
+        """(dP, C_d, R_s, sigma_s, R_e, delta) of the current state (d=3, cubic domain)."""
+        L = lib()
+        L.orc_droplet_obs3d.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                        ctypes.c_int] + [ctypes.c_void_p] * 3 + [ctypes.c_int] * 4 + [ctypes.c_void_p]
+        out = np.zeros(6)
+        assert self.d == 3 and self.nx == self.ny == self.nz
+        rc = L.orc_droplet_obs3d(self.nx, self.G, self.kind, self.p, len(self.codes), self.codes.ctypes.data,
+                                 self.W.ctypes.data, self.f.ctypes.data, int(center[0]), int(center[1]),
+                                 int(center[2]), int(bool(bubble)), out.ctypes.data)
+        assert rc == 0
+        return out
+
     def droplet_observables(self, center, bubble=False):
         """(dP, C_d, R_s, sigma_s, R_e, R_e - R_s) of the current state (d=2, square domain)."""
         L = lib()

@@ -328,6 +328,107 @@ static void ptensor2d_cell(const Geom& g, const Stencil& st, const int* codes, c
   out[2] = pre * xy;
 }
 
+// ---------------------------------------------------------------- lattice pressure tensor, d = 2, 3
+// One rule for every group of the appendices on the lattice pressure tensor: the interaction
+// of a link from site y to y + e (weight W(|e|^2), ordered: the -e vector gives the reverse
+// link) is shared along the link. With K = max_i |e_i|, the link contributes at the K points
+// p_m = y + m e / K, m = 0 .. K-1, a share 1/(2K) each; a point that is not a lattice site
+// (q non-integer coordinates) hands its share in equal parts to the 2^q sites around it:
+//   P^{mu nu}(x) = n c^2 delta + G c^2 sum_e W e^mu e^nu sum_m (1/(2K)) sum_{corners c of p_m}
+//                   2^{-q} psi(x - c) psi(x - c + e).
+// For e along a line (e = K e_hat) this is the line rule of the symmetric groups (psi(x) psi(x+e)
+// and psi(x + e/2) psi(x - e/2) for |e|^2 = 4, 8; the e/3 forms for 9, 18; the e/4 forms for 16,
+// each after the +-e sum); for the groups (2,1,0), (2,1,1), (2,2,1) m = 0 is their regular part
+// and m = 1 (the crossing of the plane midway) their irregular pairs: the two sites around
+// (1, 1/2, 0) with share 1/8 per ordered vector (W/4 per pair), the four around (1, 1/2, 1/2)
+// (W/8 per pair), the two around (1, 1, 1/2) (W/4 per pair). Out: xx, yy, zz, xy, xz, yz.
+template <class T>
+static void ptensor_cell(const Geom& g, const Stencil& st, const T* W, const T& G, const std::vector<T>& n,
+                         const std::vector<T>& psi, long c, T out[6]) {
+  long x, y, z;
+  g.coords(c, x, y, z);
+  T acc[6] = {T(0.0), T(0.0), T(0.0), T(0.0), T(0.0), T(0.0)};
+  for (size_t a = 0; a < st.e.size(); ++a) {
+    const long e[3] = {st.e[a][0], st.e[a][1], st.e[a][2]};
+    const long K = std::max(std::labs(e[0]), std::max(std::labs(e[1]), std::labs(e[2])));
+    T link(0.0);  // sum over m and corners of the weighted psi psi products
+    for (long m = 0; m < K; ++m) {
+      // p_m = m e / K: integer part and whether the coordinate is a half-integer or integer
+      long base[3];
+      bool frac[3];
+      int q = 0;
+      for (int i = 0; i < 3; ++i) {
+        const long num = m * e[i];
+        frac[i] = num % K != 0;
+        base[i] = (long)std::floor((double)num / (double)K);
+        q += frac[i] ? 1 : 0;
+      }
+      const double share = 1.0 / (2.0 * (double)K) / (double)(1 << q);
+      for (int bits = 0; bits < 8; ++bits) {
+        bool ok = true;
+        long cc[3];
+        for (int i = 0; i < 3; ++i) {
+          const int b = (bits >> i) & 1;
+          if (!frac[i] && b) { ok = false; break; }
+          cc[i] = base[i] + b;
+        }
+        if (!ok) continue;
+        const long y0[3] = {x - cc[0], y - cc[1], z - cc[2]};
+        link = link + share * psi[g.idx(y0[0], y0[1], y0[2])] * psi[g.idx(y0[0] + e[0], y0[1] + e[1], y0[2] + e[2])];
+      }
+    }
+    const T t = W[st.shell[a]] * link;
+    acc[0] = acc[0] + t * (double)(e[0] * e[0]);
+    acc[1] = acc[1] + t * (double)(e[1] * e[1]);
+    acc[2] = acc[2] + t * (double)(e[2] * e[2]);
+    acc[3] = acc[3] + t * (double)(e[0] * e[1]);
+    acc[4] = acc[4] + t * (double)(e[0] * e[2]);
+    acc[5] = acc[5] + t * (double)(e[1] * e[2]);
+  }
+  const T pre = G * CS2;
+  for (int k = 0; k < 6; ++k) out[k] = pre * acc[k];
+  for (int k = 0; k < 3; ++k) out[k] = out[k] + n[c] * CS2;
+}
+
+// ---------------------------------------------------------------- droplet observables, d = 3
+// As in d = 2 with Pbar = tr P / 3, P_T = P^yy on the +-x half-lines through the centre,
+// C_d = int_0^{L/2} r^2 (Pbar(corner) - P_T(r)) dr, R_s = (6 C_d / Delta P)^{1/3},
+// sigma_s = Delta P R_s / 2 and (4/3) pi R_e^3 n_in + (L^3 - (4/3) pi R_e^3) n_out = M.
+template <class T>
+static void droplet_obs3d(const Geom& g, const Stencil& st, const T* W, const T& G, const std::vector<T>& n,
+                          const std::vector<T>& psi, int cx, int cy, int cz, int bubble, T out[6]) {
+  const int L = g.nx;
+  T Pc[6], Po[6];
+  ptensor_cell(g, st, W, G, n, psi, g.idx(cx, cy, cz), Pc);
+  ptensor_cell(g, st, W, G, n, psi, g.idx(0, 0, 0), Po);
+  const T Pbar_c = (Pc[0] + Pc[1] + Pc[2]) / 3.0;
+  const T Pbar_o = (Po[0] + Po[1] + Po[2]) / 3.0;
+  const T dP = Pbar_c - Pbar_o;
+  const int R = L / 2;
+  T Cd(0.0);
+  for (int sgn = -1; sgn <= 1; sgn += 2) {
+    T sum(0.0);
+    for (int r = 0; r <= R; ++r) {
+      T P[6];
+      ptensor_cell(g, st, W, G, n, psi, g.idx(cx + sgn * r, cy, cz), P);
+      T gr = (double)r * (double)r * (Pbar_o - P[1]);
+      if (r == 0 || r == R) gr = 0.5 * gr;
+      sum = sum + gr;
+    }
+    Cd = Cd + 0.5 * sum;
+  }
+  const T Rs = cbrt(6.0 * Cd / dP);
+  const T sig = 0.5 * dP * Rs;
+  T M(0.0);
+  for (long c = 0; c < g.N(); ++c) M = M + n[c];
+  const T nin = n[g.idx(cx, cy, cz)];
+  const T nout = n[0];
+  const double PI = 3.14159265358979323846;
+  const double L3 = (double)L * (double)L * (double)L;
+  const T Re = cbrt((M - L3 * nout) / ((4.0 / 3.0) * PI * (nin - nout)));
+  out[0] = dP; out[1] = Cd; out[2] = Rs; out[3] = sig; out[4] = Re; out[5] = (bubble ? -1.0 : 1.0) * (Re - Rs);
+}
+
 // ---------------------------------------------------------------- droplet observables, d = 2
 // Inputs: square L x L domain, centre (cx, cy), b = 1 for a bubble.
 //   Pbar = tr P / d; Delta P = Pbar(centre) - Pbar(corner (0,0)).
@@ -481,6 +582,41 @@ int orc_ptensor2d(int nx, int ny, double G, int kind, double p, int nshells, con
     ptensor2d_cell<double>(g, st, codes, W, G, n, psi, c, P);
     out[c] = P[0]; out[N + c] = P[1]; out[2 * N + c] = P[2];
   }
+  return 0;
+}
+
+// Lattice pressure tensor by the link-sharing rule (d = 2 or 3): out holds 6 planes of N
+// values (xx, yy, zz, xy, xz, yz).
+int orc_ptensor(int d, int nx, int ny, int nz, double G, int kind, double p, int nshells, const int* codes,
+                const double* W, const double* f, double* out) {
+  VelSet vs = make_velset(d);
+  Stencil st;
+  if (!make_stencil(d, nshells, codes, st)) return -1;
+  Geom g{d, nx, ny, nz};
+  std::vector<double> n, j, psi, F;
+  macro_fields<double>(g, vs, st, W, G, kind, p, f, n, j, psi, F);
+  const long N = g.N();
+#pragma omp parallel for schedule(static)
+  for (long c = 0; c < N; ++c) {
+    double P[6];
+    ptensor_cell<double>(g, st, W, G, n, psi, c, P);
+    for (int k = 0; k < 6; ++k) out[k * N + c] = P[k];
+  }
+  return 0;
+}
+
+// Droplet observables (d = 3, cubic domain) of a state f: out = (dP, C_d, R_s, sigma_s, R_e, delta).
+int orc_droplet_obs3d(int n_, double G, int kind, double p, int nshells, const int* codes, const double* W,
+                      const double* f, int cx, int cy, int cz, int bubble, double* out) {
+  VelSet vs = make_velset(3);
+  Stencil st;
+  if (!make_stencil(3, nshells, codes, st)) return -1;
+  Geom g{3, n_, n_, n_};
+  std::vector<double> n, j, psi, F;
+  macro_fields<double>(g, vs, st, W, G, kind, p, f, n, j, psi, F);
+  double o[6];
+  droplet_obs3d<double>(g, st, W, G, n, psi, cx, cy, cz, bubble, o);
+  for (int k = 0; k < 6; ++k) out[k] = o[k];
   return 0;
 }
 

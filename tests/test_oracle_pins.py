@@ -495,3 +495,74 @@ def test_tangent_linear_matches_finite_differences():
         fd = (run(Wp, Gp) - run(Wm, Gm)) / (2 * h)
         scale = np.abs(jac[:, q]).max()
         assert np.abs(fd - jac[:, q]).max() < 1e-5 * scale + 1e-9, q
+
+
+def _mixed_coefficient(d, code, a, b, comps):
+    """Coefficient of psi_a psi_b in the oracle's P^{mu nu}(x = 0) for a one-shell stencil with
+    W = 1: the mixed second difference in (psi_a, psi_b) of the bilinear pressure tensor."""
+    L = 12
+    dims = (L,) * d
+    def P_at(da, db):
+        n = np.full(L ** d, 1.3)
+        def site(v):
+            v = [c % L for c in v]
+            return v[0] + L * (v[1] + (L * v[2] if d == 3 else 0))
+        n[site(a)] += da
+        n[site(b)] += db
+        s = oracle.Sim(dims, 1.0, -1.0, [code], [1.0]).init_density(n)
+        return s.pressure_tensor_general()[:, 0]
+    h = 0.05
+    m = (P_at(h, h) - P_at(h, 0) - P_at(0, h) + P_at(0, 0))
+    dpa = math.exp(-1 / (1.3 + h)) - math.exp(-1 / 1.3)
+    return m[comps] / (dpa * dpa)
+
+
+def test_pressure_tensor_3d_pairs_match_appendix():
+    """App. LPT d = 3: the oracle's link-sharing tensor puts on each printed pair psi_a psi_b the
+    printed coefficient, G c^2 W c e^mu e^nu (G = -1, W = 1), in every component, and nothing on a
+    pair the appendix does not list (a link away from x)."""
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "lpt3d_pairs.json")))
+    for ent in gold["pairs"]:
+        e = np.array(ent["e"], dtype=float)
+        want = -CS2 * ent["c"] * np.array([e[0] * e[0], e[1] * e[1], e[2] * e[2], e[0] * e[1], e[0] * e[2], e[1] * e[2]])
+        code = 1009 if ent["code"] == 9 and sorted(np.abs(e)) == [0, 0, 3] else ent["code"]
+        got = _mixed_coefficient(3, code, ent["a"], ent["b"], slice(0, 6))
+        assert np.abs(got - want).max() < 1e-9 * max(1.0, np.abs(want).max()), ent
+    # a link of the (2,1,1) group that neither starts at x nor crosses next to it
+    got = _mixed_coefficient(3, 6, [1, 0, 0], [3, 1, 1], slice(0, 6))
+    assert np.abs(got).max() < 1e-12
+
+
+def test_pressure_tensor_general_rule_equals_printed_2d():
+    """In d = 2 the link-sharing rule reproduces the appendix's printed groups and irregular
+    |e|^2 = 5 pairs, implemented separately from the printed formulas."""
+    codes = [1, 2, 4, 5, 8, 9, 16, 18]
+    W = [0.31, 0.07, -0.02, 0.013, 0.004, 0.002, -0.001, 0.0005]
+    n0 = synth.uniform((20, 18), 0.6, 1.6, seed=12)
+    s = oracle.Sim((20, 18), 1.0, -8.0, codes, W).init_density(n0)
+    P2 = s.pressure_tensor()
+    Pg = s.pressure_tensor_general()
+    assert np.abs(Pg[0] - P2[0]).max() < 1e-14
+    assert np.abs(Pg[1] - P2[1]).max() < 1e-14
+    assert np.abs(Pg[3] - P2[2]).max() < 1e-14
+    assert np.abs(Pg[2] - 1.0 / 3.0 * s.fields()["n"]).max() < 1e-15   # no z-component in 2D
+
+
+def test_pressure_tensor_3d_flat_interface_equilibrium():
+    """Mechanical equilibrium in d = 3 (Sec. Interface Physics): a converged flat slab of the
+    3D E(8) stencil (92 vectors, with the irregular groups (2,1,0) and (2,1,1)) has P_N constant
+    to machine precision and isotropic bulk values."""
+    from paper_2505_23647_amd import stencil
+    W = stencil.family3d(4 / 7, 16 / 105, 1 / 630)
+    G = thermo.G_for_reduced_temperature(0.2)
+    ng, nl, _ = thermo.coexistence(G, e4=4 / 7)
+    nx = 48
+    n0 = np.tile(synth.slab(nx, nl, ng, 12.0), 4 * 4)
+    s = oracle.Sim((nx, 4, 4), 1.0, G, [1, 2, 3, 4, 5, 6, 8], W).init_density(n0)
+    assert s.run(20000) == 0
+    P = s.pressure_tensor_general()
+    PN = P[0]
+    assert (PN.max() - PN.min()) < 1e-12 * abs(PN.mean())
+    assert np.abs(P[1] - P[2]).max() < 1e-13
+    assert np.abs(P[3:]).max() < 1e-13
+    assert (P[0] - P[1]).max() > 1e-3
