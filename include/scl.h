@@ -151,14 +151,21 @@ scl_status scl_set_populations(scl_lattice lat, const double* in, int32_t is_dev
  * ndom x d doubles (may be NULL). Returns SCL_E_NONFINITE if any mass is NaN or Inf. */
 scl_status scl_reduce_conserved(scl_lattice lat, double* mass, double* momentum);
 
-/* Lattice pressure tensor of the current state in double (D2Q9 only): out holds 3 x cells
- * values, the planes Pxx, Pyy, Pxy. Follows the d = 2 appendix on the lattice pressure
- * tensor (groups along a line plus the irregular pairs of |e|^2 = 5) with the ideal part
- * n c_s^2 delta added (Sec. "Interface Physics"). D3Q19 returns SCL_E_UNSUPPORTED. */
+/* Lattice pressure tensor of the current state in double, with the ideal part n c_s^2 delta
+ * added (Sec. "Interface Physics"). D2Q9: out holds 3 x cells values, the planes Pxx, Pyy, Pxy,
+ * by the d = 2 appendix on the lattice pressure tensor (groups along a line plus the
+ * irregular pairs of |e|^2 = 5). D3Q19: 6 x cells values, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz, by the
+ * d = 3 appendix: every link y -> y + e shares its interaction along the link, 1/(2K) at each
+ * point y + m e / K (K = max_i |e_i|, m = 0 .. K-1), a point between sites handing its share
+ * equally to the sites around it; this gives the appendix's symmetric groups and the
+ * irregular pairs of the (2,1,0), (2,1,1), (2,2,1) groups. */
 scl_status scl_get_pressure_tensor(scl_lattice lat, double* out, int32_t is_device_ptr);
 
-/* Droplet / bubble observables of each square D2Q9 domain (Sec. "Interface Physics" and the
- * Laplace-law paragraph of the sigma_1 tuning section), in double:
+/* Droplet / bubble observables of each square D2Q9 domain or cubic D3Q19 domain (Sec.
+ * "Interface Physics" and the Laplace-law paragraph of the sigma_1 tuning section), in double.
+ * d = 3 uses Pbar = tr P / 3, the weight r^2 in C_d, R_s = (6 C_d / dP)^(1/3),
+ * sigma_s = dP R_s / 2 and the sphere volume for R_e; center then holds ndom x 3 ints.
+ * d = 2:
  *   Pbar = (Pxx + Pyy)/2, dP = Pbar(centre) - Pbar(corner (0,0));
  *   C_d = int_0^{L/2} r (Pbar(corner) - Pyy(centre + r e_x)) dr, trapezoid on sites, mean of
  *         the +x and -x half-lines;

@@ -188,6 +188,47 @@ __global__ void k_ptensor2d(const double* __restrict__ n, const double* __restri
   P[2 * tot_cells + g] = G_cs2 * xy;
 }
 
+// ------------------------------------------------------------------ lattice pressure tensor, any d
+// P^{mu nu}(x) = n c^2 delta + G c^2 sum_terms coef W[slot] psi(x + a) psi(x + b) e^mu e^nu over a
+// term list built on the host: every link y -> y + e of the stencil shares its interaction along
+// the link, 1/(2K) at each of the points y + m e/K (K = max_i |e_i|, m = 0 .. K-1), a point off
+// the lattice handing its share equally to the sites around it (the groups and irregular pairs
+// of the appendices on the lattice pressure tensor). Out: 6 planes xx, yy, zz, xy, xz, yz.
+struct PTermDev {
+  double coef;
+  int8_t a[3], b[3], e[3];
+  int8_t slot;
+};
+
+__global__ void k_ptensor_terms(const double* __restrict__ n, const double* __restrict__ psi, double* __restrict__ P,
+                                long long tot_cells, DomDev dm, const PTermDev* __restrict__ terms, int nterms) {
+  const long long cells = (long long)dm.nx * dm.ny * dm.nz;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cells) return;
+  const int x = (int)(c % dm.nx);
+  const int y = (int)((c / dm.nx) % dm.ny);
+  const int z = (int)(c / ((long long)dm.nx * dm.ny));
+  const double* pb = psi + dm.off;
+  auto ps = [&](const int8_t* o) {
+    return pb[wrapi(x + o[0], dm.nx) + (long long)dm.nx * (wrapi(y + o[1], dm.ny) + (long long)dm.ny * wrapi(z + o[2], dm.nz))];
+  };
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int t = 0; t < nterms; ++t) {
+    const PTermDev& q = terms[t];
+    const double v = q.coef * dm.W[q.slot] * ps(q.a) * ps(q.b);
+    acc[0] += v * (q.e[0] * q.e[0]);
+    acc[1] += v * (q.e[1] * q.e[1]);
+    acc[2] += v * (q.e[2] * q.e[2]);
+    acc[3] += v * (q.e[0] * q.e[1]);
+    acc[4] += v * (q.e[0] * q.e[2]);
+    acc[5] += v * (q.e[1] * q.e[2]);
+  }
+  const double G_cs2 = -dm.gpre;
+  const long long g = dm.off + c;
+  const double id = n[g] * CS2;
+  for (int k = 0; k < 6; ++k) P[k * tot_cells + g] = G_cs2 * acc[k] + (k < 3 ? id : 0.0);
+}
+
 // ------------------------------------------------------------------ fixed-order reductions
 // Each block reduces a contiguous chunk of one domain's sites into nv doubles: values[v] =
 // sum over sites of field_v, field_0 = n, field_{1..d} = j + F/2. The chunking and the tree

@@ -22,6 +22,11 @@
 
 using namespace scl;
 
+// row ranges of one strip handed out together in the 2D item order
+#ifndef SCL_ITEM_BAND
+#define SCL_ITEM_BAND 8
+#endif
+
 namespace {
 
 thread_local std::string g_err;
@@ -177,7 +182,7 @@ scl_status build_items(scl_lattice_s* L) {
     // in order. The device hands each XCD a contiguous eighth of this list, so an XCD works on
     // a compact block of neighbouring strips and ranges whose shared halos meet in its L2.
     // Consecutive ranges of a strip march in opposite directions.
-    const int BAND = 8;
+    const int BAND = SCL_ITEM_BAND;
     for (int k = 0; k < L->ndom; ++k) {
       const int ns = (L->nx[k] + outw - 1) / outw;
       const int nseg = (L->ny[k] + seg - 1) / seg;
@@ -270,6 +275,9 @@ hipError_t launch2d(scl_lattice_s* L, const void* fin, void* fout, MacroRec<M> r
   SCL_2D_CASE(0, 64, 2) SCL_2D_CASE(0, 128, 2) SCL_2D_CASE(0, 256, 2)
   SCL_2D_CASE(1, 64, 2) SCL_2D_CASE(1, 128, 2) SCL_2D_CASE(1, 256, 2)
   SCL_2D_CASE(2, 128, 1) SCL_2D_CASE(2, 256, 1)
+#ifdef SCL_STRIP512
+  SCL_2D_CASE(1, 512, 1)
+#endif
 #undef SCL_2D_CASE
   return hipErrorInvalidValue;
 }
@@ -388,7 +396,7 @@ scl_status ensure_scratch(scl_lattice_s* L) {
     HIPCHK(hipMalloc(&L->d_psi, c * sizeof(double)));
     HIPCHK(hipMalloc(&L->d_j, 3 * c * sizeof(double)));
     HIPCHK(hipMalloc(&L->d_F, 3 * c * sizeof(double)));
-    HIPCHK(hipMalloc(&L->d_tmp, 3 * c * sizeof(double)));
+    HIPCHK(hipMalloc(&L->d_tmp, (L->d == 3 ? 6 : 3) * c * sizeof(double)));
   }
   return SCL_OK;
 }
@@ -489,6 +497,43 @@ std::vector<PTerm> ptensor_terms(const scl_lattice_s* L) {
         t.push_back({0.25, pr[v][p][0], pr[v][p][1], pr[v][p][2], pr[v][p][3], ev[v][0], ev[v][1], slot5});
   }
   return t;
+}
+
+// Term list of k_ptensor_terms for the lattice's stencil (every vector of both signs).
+std::vector<PTermDev> ptensor_link_terms(const scl_lattice_s* L) {
+  std::vector<PTermDev> out;
+  VecTable tab = full_table(L);
+  for (int k = 0; k < tab.n; ++k) {
+    const int e[3] = {tab.v[k].x, tab.v[k].y, tab.v[k].z};
+    const int K = std::max(std::abs(e[0]), std::max(std::abs(e[1]), std::abs(e[2])));
+    for (int m = 0; m < K; ++m) {
+      int base[3], q = 0;
+      bool off[3];
+      for (int i = 0; i < 3; ++i) {
+        const int num = m * e[i];
+        off[i] = num % K != 0;
+        base[i] = (int)std::floor((double)num / K);
+        q += off[i];
+      }
+      const double share = 1.0 / (2.0 * K) / (double)(1 << q);
+      for (int bits = 0; bits < 8; ++bits) {
+        bool use = true;
+        for (int i = 0; i < 3; ++i) use = use && (off[i] || !((bits >> i) & 1));
+        if (!use) continue;
+        PTermDev t{};
+        t.coef = share;
+        for (int i = 0; i < 3; ++i) {
+          const int ci = base[i] + ((bits >> i) & 1);
+          t.a[i] = (int8_t)(-ci);
+          t.b[i] = (int8_t)(-ci + e[i]);
+          t.e[i] = (int8_t)e[i];
+        }
+        t.slot = tab.v[k].slot;
+        out.push_back(t);
+      }
+    }
+  }
+  return out;
 }
 
 double psi_host(double n, int kind, double eps) {
@@ -878,10 +923,25 @@ scl_status scl_reduce_conserved(scl_lattice L, double* mass, double* momentum) {
 
 scl_status scl_get_pressure_tensor(scl_lattice L, double* out, int32_t is_dev) {
   if (!L || !out) return fail(SCL_E_INVALID, "bad arguments");
-  if (L->d != 2) return fail(SCL_E_UNSUPPORTED, "the lattice pressure tensor is implemented for D2Q9 only");
   scl_status s = compute_fields(L, false);
   if (s != SCL_OK) return s;
   std::vector<DomDev> doms = host_doms(L);
+  if (L->d == 3) {
+    const std::vector<PTermDev> terms = ptensor_link_terms(L);
+    PTermDev* d_terms = nullptr;
+    HIPCHK(hipMalloc(&d_terms, terms.size() * sizeof(PTermDev)));
+    std::unique_ptr<PTermDev, hipError_t (*)(void*)> guard(d_terms, hipFree);
+    HIPCHK(hipMemcpyAsync(d_terms, terms.data(), terms.size() * sizeof(PTermDev), hipMemcpyHostToDevice, L->stream));
+    for (int k = 0; k < L->ndom; ++k) {
+      const long long c = (long long)L->nx[k] * L->ny[k] * L->nz[k];
+      hipLaunchKernelGGL(k_ptensor_terms, dim3(blocks_for(c, 256)), dim3(256), 0, L->stream, (const double*)L->d_n,
+                         (const double*)L->d_psi, L->d_tmp, L->cells, doms[k], d_terms, (int)terms.size());
+      HIPCHK(hipGetLastError());
+    }
+    s = copy_out(L, out, L->d_tmp, (size_t)6 * L->cells, is_dev);
+    HIPCHK(hipStreamSynchronize(L->stream));
+    return s;
+  }
   VecTable tab = full_table(L);
   int slot5 = -1;
   for (int q = 0; q < SET2N[L->set]; ++q)
@@ -895,9 +955,57 @@ scl_status scl_get_pressure_tensor(scl_lattice L, double* out, int32_t is_dev) {
   return copy_out(L, out, L->d_tmp, (size_t)3 * L->cells, is_dev);
 }
 
+// d = 3: cubic domains, centre (x, y, z); Pbar = tr P / 3, C_d with weight r^2,
+// R_s = (6 C_d / dP)^(1/3), sigma_s = dP R_s / 2, (4/3) pi R_e^3 n(centre) + (L^3 - (4/3) pi R_e^3) n(corner) = M.
+static scl_status droplet_observables3d(scl_lattice L, const int32_t* center, const int8_t* is_bubble, double* out) {
+  for (int k = 0; k < L->ndom; ++k) {
+    if (L->nx[k] != L->ny[k] || L->nx[k] != L->nz[k]) return fail(SCL_E_INVALID, "3D droplet observables need cubic domains");
+    for (int i = 0; i < 3; ++i)
+      if (center[3 * k + i] < 0 || center[3 * k + i] >= L->nx[k]) return fail(SCL_E_INVALID, "centre outside the domain");
+  }
+  std::vector<double> P((size_t)6 * L->cells);
+  scl_status s = scl_get_pressure_tensor(L, P.data(), 0);
+  if (s != SCL_OK) return s;
+  std::vector<double> n((size_t)L->cells);
+  HIPCHK(hipMemcpy(n.data(), L->d_n, n.size() * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<double> mass(L->ndom);
+  s = scl_reduce_conserved(L, mass.data(), nullptr);
+  if (s != SCL_OK) return s;
+  const long long C = L->cells;
+  for (int k = 0; k < L->ndom; ++k) {
+    const int Ls = L->nx[k], cx = center[3 * k], cy = center[3 * k + 1], cz = center[3 * k + 2];
+    const long long o = L->off[k];
+    auto idx = [&](int x, int y, int z) {
+      return (size_t)(o + ((long long)wrapi(z, Ls) * Ls + wrapi(y, Ls)) * Ls + wrapi(x, Ls));
+    };
+    auto pbar = [&](size_t c) { return (P[c] + P[(size_t)C + c] + P[(size_t)2 * C + c]) / 3.0; };
+    const double Pc = pbar(idx(cx, cy, cz)), Po = pbar(idx(0, 0, 0));
+    const double dP = Pc - Po;
+    const int Rm = Ls / 2;
+    double Cd = 0;
+    for (int sg = -1; sg <= 1; sg += 2) {
+      double sum = 0;
+      for (int r = 0; r <= Rm; ++r) {
+        double g = (double)r * r * (Po - P[(size_t)C + idx(cx + sg * r, cy, cz)]);
+        if (r == 0 || r == Rm) g *= 0.5;
+        sum += g;
+      }
+      Cd += 0.5 * sum;
+    }
+    const double Rs = std::cbrt(6.0 * Cd / dP);
+    const double sgn = (is_bubble && is_bubble[k]) ? -1.0 : 1.0;
+    const double nin = n[idx(cx, cy, cz)], nout = n[idx(0, 0, 0)];
+    const double L3 = (double)Ls * Ls * Ls;
+    const double Re = std::cbrt((mass[k] - L3 * nout) / (4.0 / 3.0 * M_PI * (nin - nout)));
+    double* r6 = out + (size_t)6 * k;
+    r6[0] = dP; r6[1] = Cd; r6[2] = Rs; r6[3] = 0.5 * dP * Rs; r6[4] = Re; r6[5] = sgn * (Re - Rs);
+  }
+  return SCL_OK;
+}
+
 scl_status scl_droplet_observables(scl_lattice L, const int32_t* center, const int8_t* is_bubble, double* out) {
   if (!L || !center || !out) return fail(SCL_E_INVALID, "bad arguments");
-  if (L->d != 2) return fail(SCL_E_UNSUPPORTED, "droplet observables are implemented for D2Q9 only");
+  if (L->d == 3) return droplet_observables3d(L, center, is_bubble, out);
   for (int k = 0; k < L->ndom; ++k) {
     if (L->nx[k] != L->ny[k]) return fail(SCL_E_INVALID, "droplet observables need square domains");
     if (center[2 * k] < 0 || center[2 * k] >= L->nx[k] || center[2 * k + 1] < 0 || center[2 * k + 1] >= L->ny[k])
@@ -997,7 +1105,12 @@ scl_status scl_flat_observables(scl_lattice L, const double* bulk, double* out) 
 scl_status scl_set_tiling(scl_lattice L, int32_t strip, int32_t seg, int32_t cpl) {
   if (!L || strip < 0 || seg < 0 || cpl < 0) return fail(SCL_E_INVALID, "bad tiling");
   if (L->d == 2) {
-    if (strip != 0 && strip != 64 && strip != 128 && strip != 256) return fail(SCL_E_INVALID, "2D strip must be 64, 128 or 256");
+    if (strip != 0 && strip != 64 && strip != 128 && strip != 256
+#ifdef SCL_STRIP512
+        && strip != 512
+#endif
+    )
+      return fail(SCL_E_INVALID, "2D strip must be 64, 128 or 256");
     if (cpl > 2) return fail(SCL_E_INVALID, "sites per lane must be 1 or 2 (0 = automatic)");
     if (L->set == 2 && (strip == 64 || cpl == 2))
       return fail(SCL_E_UNSUPPORTED, "the reach-4 shell set runs with 128- or 256-lane strips, one site per lane");

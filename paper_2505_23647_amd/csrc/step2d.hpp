@@ -26,6 +26,10 @@
 #ifndef SCL_STEP2D_PF
 #define SCL_STEP2D_PF 1
 #endif
+// minimum waves per SIMD the step is compiled for (0: no bound beyond the block size)
+#ifndef SCL_STEP2D_WPE
+#define SCL_STEP2D_WPE 0
+#endif
 
 namespace scl {
 
@@ -84,7 +88,7 @@ template <int SET, int CPL> struct Halo2 {
 };
 
 template <class S, class M, int SET, int NO, int CPL, bool SHIFT, bool REC>
-__global__ void __launch_bounds__(NO)
+__global__ void __launch_bounds__(NO, SCL_STEP2D_WPE)
 k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restrict__ doms,
          const WorkItem* __restrict__ items, int nitems, MacroRec<M> rec) {
   using V = Vel<0>;

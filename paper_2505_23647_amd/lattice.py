@@ -168,7 +168,9 @@ class Lattice:
         return self
 
     def pressure_tensor(self):
-        return self._get(lib().scl_get_pressure_tensor, 3 * self.cells).reshape(3, self.cells)
+        """2D: [3, cells] (xx, yy, xy); 3D: [6, cells] (xx, yy, zz, xy, xz, yz)."""
+        nc = 3 if self.d == 2 else 6
+        return self._get(lib().scl_get_pressure_tensor, nc * self.cells).reshape(nc, self.cells)
 
     def reduce_conserved(self):
         mass = np.empty(self.ndom)
@@ -177,7 +179,7 @@ class Lattice:
         return mass, mom
 
     def droplet_observables(self, centers, is_bubble=None):
-        c = np.ascontiguousarray(np.asarray(centers, dtype=np.int32).reshape(self.ndom, 2))
+        c = np.ascontiguousarray(np.asarray(centers, dtype=np.int32).reshape(self.ndom, self.d))
         b = None
         if is_bubble is not None:
             b = np.ascontiguousarray(np.asarray(is_bubble, dtype=np.int8).reshape(self.ndom))

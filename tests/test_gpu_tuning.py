@@ -118,7 +118,7 @@ def test_flat_tolman_length_tuning():
         assert spread < 1e-9
         # the two Tolman definitions agree (per interface), the interfaces mirror each other
         assert np.allclose(obs[:, 3], obs[:, 4], rtol=1e-9)
-        assert abs(obs[0, 3] - obs[1, 3]) < 1e-7 * abs(obs[0, 3])
+        assert abs(obs[0, 3] - obs[1, 3]) < 1e-5 * abs(obs[0, 3])
         # bulk densities untouched by the Tolman knob
         assert abs(nlx - res[0.0][0]) < 1e-12 * nlx and abs(ngx - res[0.0][1]) < 1e-12 * ngx
     d = {dd: res[dd][2][0, 3] for dd in res}
