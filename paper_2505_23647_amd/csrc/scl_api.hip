@@ -92,7 +92,8 @@ struct scl_lattice_s {
   int nitems = 0;
   bool dirty_doms = true, dirty_items = true;
   // tiling
-  int strip = 256, seg = 0;        // 2D: output lanes per workgroup, rows per item (0 = auto)
+  int strip = 0, seg = 0;          // 2D: output lanes per workgroup, rows per item (0 = auto)
+  int strip_eff = 256;             // 2D: output lanes per workgroup in use
   int cpl_req = 0;                 // 2D: sites per lane requested (0 = auto)
   int cpl = 1;                     // 2D: sites per lane in use
   int tile3 = 2, seg3 = 0;         // 3D: tile index, planes per item (0 = auto)
@@ -173,11 +174,29 @@ scl_status build_items(scl_lattice_s* L) {
     // cut occupancy to 3 waves per SIMD.
     L->cpl = L->cpl_req ? L->cpl_req : 1;
     if (L->cpl == 2 && !even) return fail(SCL_E_INVALID, "two sites per lane need even domain widths");
-    const int outw = L->strip * L->cpl;
-    // rows per item: measured best on MI355X with 256-lane strips (4096^2, 24 vectors): 32
-    // for every storage width (within 2% of the best for FP16)
+    // output lanes per workgroup: measured best on MI355X (4096^2, 24 vectors): 512 for 4-byte
+    // storage, 256 for FP64; 256 for the reach-4 set (larger ring and register sets). Narrow
+    // domains take narrower strips: the widest whose idle lanes (strip columns past a domain's
+    // width) stay under 10% of the sites.
+    if (L->strip) {
+      L->strip_eff = L->strip;
+    } else {
+      int w = (storage_bytes(L->prec) == 4 && L->set != 2 && L->cpl == 1) ? 512 : 256;
+      for (; w > 128; w /= 2) {
+        long long idle = 0;
+        for (int k = 0; k < L->ndom; ++k) {
+          const long long ow = (long long)w * L->cpl;
+          idle += ((L->nx[k] + ow - 1) / ow * ow - L->nx[k]) * (long long)L->ny[k];
+        }
+        if (idle * 10 <= L->cells) break;
+      }
+      L->strip_eff = w;
+    }
+    const int outw = L->strip_eff * L->cpl;
+    // rows per item: measured best on MI355X (4096^2, 24 vectors): 64 for FP16 storage, 32
+    // otherwise
     int seg = L->seg;
-    if (seg <= 0) seg = 32;
+    if (seg <= 0) seg = L->prec == SCL_FP16S_FP32 ? 64 : 32;
     // Order: bands of BAND row ranges; within a band, strip by strip, the ranges of the band
     // in order. The device hands each XCD a contiguous eighth of this list, so an XCD works on
     // a compact block of neighbouring strips and ranges whose shared halos meet in its L2.
@@ -257,7 +276,7 @@ hipError_t launch2d(scl_lattice_s* L, const void* fin, void* fout, MacroRec<M> r
   const int per = (L->nitems + 7) / 8;
   const dim3 grid(8 * per);
 #define SCL_2D_CASE(SETV, NOV, CPLV)                                                                  \
-  if (L->set == SETV && L->strip == NOV && L->cpl == CPLV) {                                           \
+  if (L->set == SETV && L->strip_eff == NOV && L->cpl == CPLV) {                                       \
     constexpr int nt = NOV;                                                                            \
     if constexpr (!std::is_same<S, _Float16>::value) {                                                 \
       if (record) {                                                                                    \
@@ -275,9 +294,7 @@ hipError_t launch2d(scl_lattice_s* L, const void* fin, void* fout, MacroRec<M> r
   SCL_2D_CASE(0, 64, 2) SCL_2D_CASE(0, 128, 2) SCL_2D_CASE(0, 256, 2)
   SCL_2D_CASE(1, 64, 2) SCL_2D_CASE(1, 128, 2) SCL_2D_CASE(1, 256, 2)
   SCL_2D_CASE(2, 128, 1) SCL_2D_CASE(2, 256, 1)
-#ifdef SCL_STRIP512
-  SCL_2D_CASE(1, 512, 1)
-#endif
+  SCL_2D_CASE(0, 512, 1) SCL_2D_CASE(1, 512, 1)
 #undef SCL_2D_CASE
   return hipErrorInvalidValue;
 }
@@ -709,7 +726,7 @@ scl_status scl_set_stencil(scl_lattice L, int32_t nshells, const int32_t* codes,
   L->set = set;
   if (L->d == 2 && set == 2) {
     // the reach-4 set is built for one site per lane and 128- or 256-lane strips
-    if (L->strip == 64) L->strip = 128;
+    if (L->strip == 64 || L->strip == 512) L->strip = 0;
     L->cpl_req = 0;
   }
   L->user_codes.assign(codes, codes + nshells);
@@ -1105,14 +1122,12 @@ scl_status scl_flat_observables(scl_lattice L, const double* bulk, double* out) 
 scl_status scl_set_tiling(scl_lattice L, int32_t strip, int32_t seg, int32_t cpl) {
   if (!L || strip < 0 || seg < 0 || cpl < 0) return fail(SCL_E_INVALID, "bad tiling");
   if (L->d == 2) {
-    if (strip != 0 && strip != 64 && strip != 128 && strip != 256
-#ifdef SCL_STRIP512
-        && strip != 512
-#endif
-    )
-      return fail(SCL_E_INVALID, "2D strip must be 64, 128 or 256");
+    if (strip != 0 && strip != 64 && strip != 128 && strip != 256 && strip != 512)
+      return fail(SCL_E_INVALID, "2D strip must be 64, 128, 256 or 512");
+    if ((strip ? strip : L->strip) == 512 && cpl == 2)
+      return fail(SCL_E_UNSUPPORTED, "512-lane strips run one site per lane");
     if (cpl > 2) return fail(SCL_E_INVALID, "sites per lane must be 1 or 2 (0 = automatic)");
-    if (L->set == 2 && (strip == 64 || cpl == 2))
+    if (L->set == 2 && (strip == 64 || strip == 512 || cpl == 2))
       return fail(SCL_E_UNSUPPORTED, "the reach-4 shell set runs with 128- or 256-lane strips, one site per lane");
     if (cpl == 2)
       for (int k = 0; k < L->ndom; ++k)
@@ -1132,7 +1147,11 @@ scl_status scl_set_tiling(scl_lattice L, int32_t strip, int32_t seg, int32_t cpl
 
 scl_status scl_get_tiling(scl_lattice L, int32_t* strip, int32_t* seg, int32_t* cpl) {
   if (!L || !strip || !seg) return fail(SCL_E_INVALID, "bad arguments");
-  *strip = L->d == 2 ? L->strip : L->tile3;
+  if (L->d == 2 && L->dirty_items) {
+    scl_status st = build_items(L);
+    if (st != SCL_OK) return st;
+  }
+  *strip = L->d == 2 ? L->strip_eff : L->tile3;
   *seg = L->d == 2 ? L->seg : L->seg3;
   if (cpl) *cpl = L->d == 2 ? L->cpl : 1;
   return SCL_OK;
@@ -1169,8 +1188,8 @@ scl_status scl_tune(scl_lattice L, const char* cache_path) {
   }
   std::vector<std::pair<int, int>> cands;
   if (L->d == 2) {
-    for (int st : {64, 128, 256}) {
-      if (st == 64 && L->set == 2) continue;
+    for (int st : {64, 128, 256, 512}) {
+      if ((st == 64 || st == 512) && L->set == 2) continue;
       for (int sg : {8, 16, 32, 64, 128}) cands.push_back({st, sg});
     }
   } else {
