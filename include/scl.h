@@ -28,7 +28,8 @@
  *     (1,1), (-1,1), (-1,-1), (1,-1); D3Q19 rest, +-x, +-y, +-z faces, then the 12 edges.
  *   - Shell codes name forcing-vector symmetry groups: the code is |e|^2, all vectors that a
  *     generator reaches by permutations and sign flips (Fig. 1 and Sec. on sigma_1 tuning).
- *     Supported: 2D {1,2,4,5,8}; 3D {1,2,3,4,5,6,8}.
+ *     Supported: 2D {1,2,4,5,8,9,16,18}; 3D {1,2,3,4,5,6,8,9,1009,16,18} (see
+ *     scl_set_stencil for the groups of 9, 1009, 16 and 18).
  *   - G follows eq. (sc_f): the force carries an explicit c_s^2, and the critical coupling of
  *     psi = exp(-1/n) with e_2 = 1 is G_c = -e^2.
  */
@@ -110,7 +111,11 @@ scl_status scl_set_force_squared(scl_lattice lat, const double* A);
  * domain, W laid out ndom x nshells. Weights must be finite. A shell code is |e|^2 of its
  * vectors (App. "Defining the stencil"). D2Q9 accepts 1, 2, 4, 5, 8, 9, 16, 18 (9: (3,0),
  * 16: (4,0), 18: (3,3) groups; a stencil using 9, 16 or 18 reaches 4 sites and runs with
- * 128- or 256-lane strips, one site per lane); D3Q19 accepts 1, 2, 3, 4, 5, 6, 8. */
+ * 128- or 256-lane strips, one site per lane); D3Q19 accepts 1, 2, 3, 4, 5, 6, 8 and, for
+ * the 11-shell stencil of the 3D Tolman-length tuning table (tab. e4e6e8_tuning_6_3d), 9
+ * (the (2,2,1) group), 1009 (the (3,0,0) group, also |e|^2 = 9), 16 ((4,0,0)) and 18
+ * ((3,3,0)); a 3D stencil using any of these four reaches 4 sites and runs with tiles 2
+ * and 3 (scl_set_tiling). At most 12 shells. */
 scl_status scl_set_stencil(scl_lattice lat, int32_t nshells, const int32_t* shell_codes, const double* W);
 
 /* Initial state f_i(x, 0) = w_i n0(x): the fluid at rest. n0 holds cells doubles (host, or
@@ -180,8 +185,9 @@ scl_status scl_get_pressure_tensor(scl_lattice lat, double* out, int32_t is_devi
 scl_status scl_droplet_observables(scl_lattice lat, const int32_t* center, const int8_t* is_bubble,
                                    double* out);
 
-/* Flat-interface observables of each D2Q9 domain holding a slab that varies along x (two
- * interfaces, one in each half [0, nx/2) and [nx/2, nx); profiles are means over the rows),
+/* Flat-interface observables of each domain holding a slab that varies along x (two
+ * interfaces, one in each half [0, nx/2) and [nx/2, nx); profiles are means over the rows
+ * along y, and z for D3Q19),
  * in double, from the lattice pressure tensor (Sec. "Interface Physics", Sec. "Tolman
  * Length"), per interface:
  *   sigma_0 = sum_x (P_N - P_T) (eq. sigma0pnpt), P_N = Pxx, P_T = Pyy;

@@ -52,11 +52,11 @@ size_t storage_bytes(scl_precision p) {
 }
 
 // Shell codes of the compile-time sets (index = weight slot).
-const int NSETS2 = 3, NSETS3 = 2, SETW = 8;  // sets per dimension, row width of the tables
+const int NSETS2 = 3, NSETS3 = 3, SETW = 12;  // sets per dimension, row width of the tables
 const int SET2[NSETS2][SETW] = {{1, 2}, {1, 2, 4, 5, 8}, {1, 2, 4, 5, 8, 9, 16, 18}};
 const int SET2N[NSETS2] = {2, 5, 8};
-const int SET3[NSETS3][SETW] = {{1, 2, 3}, {1, 2, 3, 4, 5, 6, 8}};
-const int SET3N[NSETS3] = {3, 7};
+const int SET3[NSETS3][SETW] = {{1, 2, 3}, {1, 2, 3, 4, 5, 6, 8}, {1, 2, 3, 4, 5, 6, 8, 9, 1009, 16, 18}};
+const int SET3N[NSETS3] = {3, 7, 11};
 
 // 3D tile shapes selectable through scl_set_tiling(strip = index).
 struct Tile3 { int tx, ty; };
@@ -318,6 +318,7 @@ hipError_t launch3d(scl_lattice_s* L, const void* fin, void* fout) {
   }
   SCL_3D_CASE(0, 1, 64, 4) SCL_3D_CASE(0, 2, 64, 8) SCL_3D_CASE(0, 3, 32, 8)
   SCL_3D_CASE(1, 1, 64, 4) SCL_3D_CASE(1, 2, 64, 8) SCL_3D_CASE(1, 3, 32, 8)
+  SCL_3D_CASE(2, 2, 64, 8) SCL_3D_CASE(2, 3, 32, 8)
 #undef SCL_3D_CASE
   return hipErrorInvalidValue;
 }
@@ -716,7 +717,7 @@ scl_status scl_set_stencil(scl_lattice L, int32_t nshells, const int32_t* codes,
   }
   if (set < 0)
     return fail(SCL_E_INVALID, std::string("unsupported shell codes") +
-                                   (L->d == 2 ? " (2D supports 1,2,4,5,8,9,16,18)" : " (3D supports 1,2,3,4,5,6,8)"));
+                                   (L->d == 2 ? " (2D supports 1,2,4,5,8,9,16,18)" : " (3D supports 1,2,3,4,5,6,8,9,1009,16,18)"));
   for (int k = 0; k < L->ndom; ++k)
     for (int s = 0; s < nshells; ++s)
       if (!std::isfinite(W[(size_t)k * nshells + s])) return fail(SCL_E_INVALID, "weights must be finite");
@@ -729,6 +730,7 @@ scl_status scl_set_stencil(scl_lattice L, int32_t nshells, const int32_t* codes,
     if (L->strip == 64 || L->strip == 512) L->strip = 0;
     L->cpl_req = 0;
   }
+  if (L->d == 3 && set == 2 && L->tile3 == 1) L->tile3 = 2;  // reach 4: 64x8 and 32x8 tiles
   L->user_codes.assign(codes, codes + nshells);
   L->slot_of_user = slot;
   std::fill(L->Wslot.begin(), L->Wslot.end(), 0.0);
@@ -1069,26 +1071,26 @@ scl_status scl_droplet_observables(scl_lattice L, const int32_t* center, const i
 
 scl_status scl_flat_observables(scl_lattice L, const double* bulk, double* out) {
   if (!L || !out) return fail(SCL_E_INVALID, "bad arguments");
-  if (L->d != 2) return fail(SCL_E_UNSUPPORTED, "flat-interface observables are implemented for D2Q9 only");
   for (int k = 0; k < L->ndom; ++k)
     if (L->nx[k] < 4 || L->nx[k] % 2) return fail(SCL_E_INVALID, "flat-interface observables need an even nx >= 4");
-  std::vector<double> P((size_t)3 * L->cells);
+  const int planes = L->d == 2 ? 3 : 6;
+  std::vector<double> P((size_t)planes * L->cells);
   scl_status s = scl_get_pressure_tensor(L, P.data(), 0);
   if (s != SCL_OK) return s;
   std::vector<double> n((size_t)L->cells);
   HIPCHK(hipMemcpy(n.data(), L->d_n, n.size() * sizeof(double), hipMemcpyDeviceToHost));
   const long long C = L->cells;
   for (int k = 0; k < L->ndom; ++k) {
-    const int nx = L->nx[k], ny = L->ny[k];
+    const int nx = L->nx[k], rows = L->ny[k] * L->nz[k];
     const long long o = L->off[k];
-    // profiles along x: means over the rows
+    // profiles along x: means over the rows (y, and z in 3D)
     std::vector<double> nb(nx, 0.0), pn(nx, 0.0), pt(nx, 0.0);
-    for (int y = 0; y < ny; ++y)
+    for (int y = 0; y < rows; ++y)
       for (int x = 0; x < nx; ++x) {
         const size_t c = (size_t)(o + (long long)y * nx + x);
-        nb[x] += n[c] / ny;
-        pn[x] += P[c] / ny;
-        pt[x] += P[(size_t)C + c] / ny;
+        nb[x] += n[c] / rows;
+        pn[x] += P[c] / rows;
+        pt[x] += P[(size_t)C + c] / rows;
       }
     double nl = bulk ? bulk[2 * k] : 0.0, ng = bulk ? bulk[2 * k + 1] : 0.0;
     if (!(nl > 0.0 && ng > 0.0)) {
@@ -1137,6 +1139,8 @@ scl_status scl_set_tiling(scl_lattice L, int32_t strip, int32_t seg, int32_t cpl
     L->cpl_req = cpl;
   } else {
     if (strip > 3) return fail(SCL_E_INVALID, "3D tile index must be 1 (64x4), 2 (64x8) or 3 (32x8)");
+    if (strip == 1 && L->set == 2)
+      return fail(SCL_E_UNSUPPORTED, "the reach-4 3D shell set runs with tiles 2 (64x8) and 3 (32x8)");
     if (strip) L->tile3 = strip;
     if (seg) L->seg3 = seg;
   }
@@ -1194,6 +1198,7 @@ scl_status scl_tune(scl_lattice L, const char* cache_path) {
     }
   } else {
     for (int t : {1, 2, 3}) {
+      if (t == 1 && L->set == 2) continue;
       for (int sg : {8, 16, 32, 64}) cands.push_back({t, sg});
     }
   }

@@ -16,7 +16,7 @@
 
 namespace scl {
 
-constexpr int MAX_SHELLS = 8;   // weight slots per domain
+constexpr int MAX_SHELLS = 12;  // weight slots per domain
 constexpr double CS2 = 1.0 / 3.0;
 
 // ------------------------------------------------------------------ velocity sets
@@ -110,7 +110,7 @@ template <> struct Shells<2, 2> {
 };
 
 // 3D half lists are generated on the host into constant tables of this size.
-constexpr int MAX_HALF_3D = 46;
+constexpr int MAX_HALF_3D = 70;
 
 // ------------------------------------------------------------------ per-domain parameters
 struct DomDev {

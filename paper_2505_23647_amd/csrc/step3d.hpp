@@ -22,12 +22,16 @@ __host__ __device__ constexpr int abs_i(int a) { return a < 0 ? -a : a; }
 __host__ __device__ constexpr Half3Table make_half3(int set) {
   Half3Table t{};
   t.n = 0;
-  constexpr int gens[7][3] = {{0, 0, 1}, {0, 1, 1}, {1, 1, 1}, {0, 0, 2}, {0, 1, 2}, {1, 1, 2}, {0, 2, 2}};
-  const int ncodes = set == 0 ? 3 : 7;
+  // generators (sorted absolute components) in slot order: 1, 2, 3, 4, 5, 6, 8, then the
+  // reach-4 shells 9 = (2,2,1), 1009 = (3,0,0), 16 = (4,0,0), 18 = (3,3,0)
+  constexpr int gens[11][3] = {{0, 0, 1}, {0, 1, 1}, {1, 1, 1}, {0, 0, 2}, {0, 1, 2}, {1, 1, 2},
+                               {0, 2, 2}, {1, 2, 2}, {0, 0, 3}, {0, 0, 4}, {0, 3, 3}};
+  const int ncodes = set == 0 ? 3 : (set == 1 ? 7 : 11);
+  const int r = set == 2 ? 4 : 2;
   for (int s = 0; s < ncodes; ++s) {
-    for (int z = -2; z <= 2; ++z)
-      for (int y = -2; y <= 2; ++y)
-        for (int x = -2; x <= 2; ++x) {
+    for (int z = -r; z <= r; ++z)
+      for (int y = -r; y <= r; ++y)
+        for (int x = -r; x <= r; ++x) {
           int a = abs_i(x), b = abs_i(y), c = abs_i(z);
           // sort a <= b <= c
           if (a > b) { int q = a; a = b; b = q; }
@@ -64,8 +68,22 @@ template <> struct Shells<3, 1> {
   }
 };
 
+// the shells of the 3D Tolman-length tuning table: R_F = 4, 140 vectors
+template <> struct Shells<3, 2> {
+  static constexpr int R = 4, NH = 70, NS = 11;
+  __host__ __device__ static constexpr int code(int s) {
+    constexpr int c[11] = {1, 2, 3, 4, 5, 6, 8, 9, 1009, 16, 18};
+    return c[s];
+  }
+  __host__ __device__ static constexpr HalfVec h(int k) {
+    constexpr Half3Table t = make_half3(2);
+    return t.v[k];
+  }
+};
+
 static_assert(make_half3(0).n == 13, "3D reach-1 half list");
 static_assert(make_half3(1).n == 46, "3D reach-2 half list");
+static_assert(make_half3(2).n == 70, "3D reach-4 half list");
 
 // ------------------------------------------------------------------ pass 1: density and psi
 // psi(x) = psi(n(x)) with n(x) = sum_i f_i(x) = sum_i A_i[x - xi_i] (the populations streaming

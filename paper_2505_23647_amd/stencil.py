@@ -133,3 +133,72 @@ def surface_tension_stencil_2d(sigma0: float, sigma1: float) -> np.ndarray:
     surface-tension tuning (Sec. "Higher-order surface tension tuning")."""
     return solve_weights_2d(TOLMAN_SHELLS_2D, {"e2": 1.0, "e4": -2.0 * sigma0, "e6": 4.0 * sigma1,
                                                "I40": 0.0, "I60": 0.0, "I80": 0.0, "I81": 0.0})
+
+
+# ---------------------------------------------------------------------- 3D tuning stencil
+# In 3D the squared length 9 holds two symmetry groups; the shell code 9 names the (2,2,1)
+# group and 1009 the (3,0,0) group, 18 is the (3,3,0) group. Moments <x^a y^b z^c> of the
+# isotropic tensors give e_2 = <x^2>, e_4 = <x^2 y^2>, e_6 = <x^2 y^2 z^2>, e_8 = <x^4 y^2 z^2>/3
+# and the isotropy conditions (each zero on an isotropic stencil)
+#   order 4:  <x^4> - 3 e_4
+#   order 6:  <x^6> - 15 e_6,  <x^4 y^2> - 3 e_6
+#   order 8:  <x^8> - 105 e_8, <x^6 y^2> - 15 e_8, <x^4 y^4> - 9 e_8
+#   order 10 (one of them): 9 <x^6 y^2 z^2> - 15 <x^4 y^4 z^2>.
+# With all conditions of orders 4 to 8 zero they span the same space as the paper's I_4,0 ...
+# I_8,2 (Appendix "Defining the stencil"). The 3D table of the Tolman-length tuning
+# (tab. e4e6e8_tuning_6_3d, 11 shells) satisfies the conditions of orders 4 to 8 and, as one
+# more equation fixing its last degree of freedom, the order-10 condition above.
+
+TOLMAN_SHELLS_3D = (1, 2, 3, 4, 5, 6, 8, 9, 1009, 16, 18)
+_GEN3 = {1: (0, 0, 1), 2: (0, 1, 1), 3: (1, 1, 1), 4: (0, 0, 2), 5: (0, 1, 2), 6: (1, 1, 2), 8: (0, 2, 2),
+         9: (1, 2, 2), 1009: (0, 0, 3), 16: (0, 0, 4), 18: (0, 3, 3)}
+
+
+def shell_vectors_3d(code: int):
+    """All integer (x, y, z) of the 3D symmetry group named by ``code``."""
+    g = _GEN3[code]
+    r = g[2]
+    return [(x, y, z) for x in range(-r, r + 1) for y in range(-r, r + 1) for z in range(-r, r + 1)
+            if sorted((abs(x), abs(y), abs(z))) == list(g)]
+
+
+def _moment_rows_3d(codes):
+    def m(a, b, c):
+        return np.array([sum(float(x) ** a * float(y) ** b * float(z) ** c for x, y, z in shell_vectors_3d(k))
+                         for k in codes])
+
+    e6 = m(2, 2, 2)
+    e8 = m(4, 2, 2) / 3
+    return {"e2": m(2, 0, 0), "e4": m(2, 2, 0), "e6": e6, "e8": e8,
+            "C40": m(4, 0, 0) - 3 * m(2, 2, 0),
+            "C60": m(6, 0, 0) - 15 * e6, "C61": m(4, 2, 0) - 3 * e6,
+            "C80": m(8, 0, 0) - 105 * e8, "C81": m(6, 2, 0) - 15 * e8, "C82": m(4, 4, 0) - 9 * e8,
+            "C10": 9 * m(6, 2, 2) - 15 * m(4, 4, 2)}
+
+
+def moments3d(codes, W):
+    """Named moments and isotropy conditions of a 3D stencil with weights W (one per shell)."""
+    rows = _moment_rows_3d(codes)
+    return {k: float(v @ np.asarray(W, dtype=np.float64)) for k, v in rows.items()}
+
+
+def solve_weights_3d(codes, targets: dict) -> np.ndarray:
+    """Weights of the 3D shells ``codes`` whose named moments take the values ``targets``
+    (exactly as many targets as shells)."""
+    if len(targets) != len(codes):
+        raise ValueError("need one target per shell")
+    rows = _moment_rows_3d(codes)
+    A = np.array([rows[k] for k in targets])
+    b = np.array([float(v) for v in targets.values()])
+    return np.linalg.solve(A, b)
+
+
+def tolman_stencil_3d(sigma0: float, sigma1: float, delta0: float) -> np.ndarray:
+    """Weights on the 3D shells of TOLMAN_SHELLS_3D with e_2 = 1, the three knobs through
+    (e_4, e_6, e_8) as in 2D (eqs. hatsigma01eI, hatdelta0eI) and the isotropy conditions of
+    orders 4, 6, 8 and the one of order 10 listed above: the 3D stencil of the paper's
+    Tolman-length tuning."""
+    e4, e6, e8 = moments_for_knobs(sigma0, sigma1, delta0)
+    return solve_weights_3d(TOLMAN_SHELLS_3D, {"e2": 1.0, "e4": e4, "e6": e6, "e8": e8, "C40": 0.0,
+                                               "C60": 0.0, "C61": 0.0, "C80": 0.0, "C81": 0.0, "C82": 0.0,
+                                               "C10": 0.0})

@@ -289,8 +289,12 @@ def test_argument_validation_and_state_errors():
         lat.init_density(bad)
     lat3 = Lattice([(8, 8, 8)], SCL_FP32)
     with pytest.raises(SclError) as e:
-        lat3.set_stencil([9], [0.1])
+        lat3.set_stencil([10], [0.1])
     assert e.value.status == B.SCL_E_INVALID
+    lat3.set_stencil([1, 2, 9], [0.1, 0.05, 0.01])  # the (2,2,1) group: reach-4 set
+    with pytest.raises(SclError) as e:
+        lat3.set_tiling(1, 0, 0)
+    assert e.value.status == B.SCL_E_UNSUPPORTED
 
 
 def test_literal_config_reports_nonfinite():

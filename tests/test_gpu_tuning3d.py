@@ -1,0 +1,138 @@
+"""The paper's 3D Tolman-length tuning stencil on the GPU: 11 shells {1,2,3,4,5,6,8, (2,2,1),
+(3,0,0), (4,0,0), (3,3,0)} (140 vectors, reach 4 sites), weights from the knob solver
+(tab. e4e6e8_tuning_6_3d).
+
+* FP64 parity with the oracle on a ragged droplet domain through both reach-4 tiles
+  (populations within 1e-12), FP32-shifted against FP64.
+* The 3D lattice pressure tensor (d = 3 appendix, link-sharing rule) with these shells against
+  the oracle's, and the flat-interface readout of a 3D slab against the oracle's flat module.
+* The flat Tolman-length tuning of Sec. "Higher-order Tolman length tuning" on 3D slabs: with
+  psi = (n/(eps+n))^(1/eps), eps = 14/29, e4 = 4/5, e6 = e4^(3/2), e8 = e4^2 as reference and
+  delta_0 = delta_0,ref (1 + Delta_delta), delta changes linearly with Delta_delta and sigma_0
+  only at the 1e-3 level. Unlike the 2D table, the 3D table's projection on a line reaches 4
+  sites, so its eighth moment follows e_8 and the flat profile moves a little: the bulk
+  densities change at the 1e-4 level (the paper's machine-precision invariance is a d = 1
+  statement). The same run on the FP64 oracle gives the values asserted here.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import flat, thermo
+from paper_2505_23647_amd import SCL_FP32_SHIFTED, SCL_FP64, Lattice, stencil, synth
+from tests.gpu_helpers import perm_to_oracle, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+SH = list(stencil.TOLMAN_SHELLS_3D)
+EPS = 14 / 29
+E4 = 0.8
+KNOB_REF = (-E4 / 2, E4 ** 1.5 / 4, 1 / 12 + 95 * E4 / 432 + 7 * E4 ** 1.5 / 72 - 5 * E4 ** 2 / 144)
+
+
+def _weights(ddelta=0.0):
+    s0, s1, d0 = KNOB_REF
+    return stencil.tolman_stencil_3d(s0, s1, d0 * (1.0 + ddelta))
+
+
+def _physics(dT):
+    G = thermo.G_for_reduced_temperature(dT, kind=1, eps=EPS)
+    ng, nl, _ = thermo.coexistence(G, kind=1, eps=EPS)
+    return G, ng, nl
+
+
+def _lattice(dims, prec, G, W, n0, tiling=None):
+    lat = Lattice([dims], prec).set_physics(1.0, G, 1, EPS).set_stencil(SH, W)
+    if tiling:
+        lat.set_tiling(*tiling)
+    return lat.init_density(n0)
+
+
+def _oracle(dims, G, W, n0, steps):
+    s = oracle.Sim(dims, 1.0, G, SH, W, oracle.PSI_EPS, EPS).init_density(n0)
+    assert s.run(steps) == 0
+    return s
+
+
+@pytest.mark.parametrize("tile", [2, 3])
+def test_reach4_3d_droplet_fp64_parity(tile):
+    say(f"case: 3D reach-4 tuning stencil droplet 30x27x23 fp64, tile {tile}")
+    G, ng, nl = _physics(0.1)
+    # in 3D the stable range of the knob is narrow (the paper notes it): from this tanh start
+    # Delta_delta in [0, 0.1] runs, -0.1 and 0.2 blow up on the oracle as on the GPU
+    W = _weights(0.1)
+    dims = (30, 27, 23)
+    n0 = synth.droplet(dims, 8.0, nl, ng, noise=1e-3, seed=9)
+    lat = _lattice(dims, SCL_FP64, G, W, n0, (tile, 5))
+    lat.step(120)
+    ora = _oracle(dims, G, W, n0, 120)
+    perm = perm_to_oracle(lat.xi, 3)
+    e = rel_err(lat.domain_populations(0)[perm], ora.f)
+    say(f"  populations rel err {e:.2e}")
+    assert e <= 1e-12
+    l32 = _lattice(dims, SCL_FP32_SHIFTED, G, W, n0, (tile, 5))
+    l32.step(120)
+    e32 = rel_err(l32.density(), lat.density())
+    say(f"  fp32 shifted vs fp64 density rel err {e32:.2e}")
+    assert e32 < 1e-4
+
+
+def test_reach4_3d_pressure_tensor_and_flat_readout():
+    say("case: 3D reach-4 pressure tensor and flat readout vs oracle, slab 64x6x5 fp64")
+    G, ng, nl = _physics(0.1)
+    W = _weights(0.0)
+    dims = (64, 6, 5)
+    n0 = np.tile(synth.slab(64, nl, ng, 16.0), 30).reshape(-1) * (1.0 + 1e-4 * synth.uniform(dims, -1.0, 1.0, seed=3))
+    lat = _lattice(dims, SCL_FP64, G, W, n0)
+    lat.step(400)
+    ora = _oracle(dims, G, W, n0, 400)
+    perm = perm_to_oracle(lat.xi, 3)
+    assert rel_err(lat.domain_populations(0)[perm], ora.f) <= 1e-12
+    P = lat.pressure_tensor()
+    s = oracle.Sim(dims, 1.0, G, SH, W, oracle.PSI_EPS, EPS)
+    s.f = np.ascontiguousarray(lat.domain_populations(0)[perm])
+    ref = s.pressure_tensor_general()
+    e = rel_err(P, ref)
+    say(f"  pressure tensor rel err {e:.2e}")
+    assert e < 1e-13
+    got = lat.flat_observables([[nl, ng]])[0]
+    n = s.fields()["n"].reshape(30, 64).mean(axis=0)
+    Pm = ref.reshape(6, 30, 64).mean(axis=1)
+    for h, (lo, hi) in enumerate(flat.halves(64)):
+        want = [flat.sigma0(Pm[0], Pm[1], lo, hi), flat.z_s(Pm[0], Pm[1], lo, hi), flat.z_e(n, lo, hi, nl, ng),
+                flat.delta_zemzs(n, Pm[0], Pm[1], lo, hi, nl, ng), flat.delta_ads(n, Pm[0], Pm[1], lo, hi, nl, ng)]
+        say(f"  interface {h}: gpu {np.array2string(got[h], precision=6)} oracle {np.array2string(np.array(want), precision=6)}")
+        np.testing.assert_allclose(got[h], want, rtol=1e-9, atol=1e-12)
+
+
+def test_flat_tolman_length_tuning_3d():
+    say("case: 3D flat Tolman tuning, Delta_delta in (-0.2, 0, 0.2), 128x4x4 slabs, 60000 steps")
+    G, ng, nl = _physics(0.1)
+    nx = 128
+    n0 = np.tile(synth.slab(nx, nl, ng, 32.0), 16).reshape(-1)
+    res = {}
+    for dd in (-0.2, 0.0, 0.2):
+        lat = _lattice((nx, 4, 4), SCL_FP64, G, _weights(dd), n0)
+        lat.set_graph_steps(100)
+        lat.step(60000)
+        n = lat.density()
+        P = lat.pressure_tensor()
+        spread = (P[0].max() - P[0].min()) / abs(P[0].mean())
+        obs = lat.flat_observables()[0]
+        res[dd] = (n.max(), n.min(), obs, spread)
+        say(f"  Delta_delta={dd:+.1f}: n_l={n.max():.12f} n_g={n.min():.12f} P_N spread {spread:.1e} "
+            f"sigma_0={obs[0, 0]:.6f} delta={obs[0, 3]:.5f} delta_ads={obs[0, 4]:.5f}")
+        lat.close()
+    for dd, (nlx, ngx, obs, spread) in res.items():
+        assert spread < 1e-9
+        assert np.allclose(obs[:, 3], obs[:, 4], rtol=1e-9)
+        assert abs(obs[0, 3] - obs[1, 3]) < 1e-5 * abs(obs[0, 3])
+        assert abs(nlx - res[0.0][0]) < 1e-3 * nlx and abs(ngx - res[0.0][1]) < 1e-3 * ngx
+    d = {dd: res[dd][2][0, 3] for dd in res}
+    sig = {dd: res[dd][2][0, 0] for dd in res}
+    slope = (d[0.2] - d[-0.2]) / (0.4 * d[0.0])
+    say(f"  delta: {d[-0.2]:.5f} {d[0.0]:.5f} {d[0.2]:.5f}; d delta / (delta d Delta_delta) = {slope:.4f}")
+    # oracle, same slabs: delta 4.5908 / 5.9946 / 7.4038, slope 1.173, linear to 0.4%
+    assert abs((d[0.2] - d[0.0]) / (d[0.0] - d[-0.2]) - 1.0) < 0.01
+    assert 1.0 < slope < 1.35
+    assert max(abs(sig[dd] / sig[0.0] - 1.0) for dd in (-0.2, 0.2)) < 1e-2

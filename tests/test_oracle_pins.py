@@ -401,6 +401,49 @@ def test_force_leading_order_taylor():
     assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
 
 
+@pytest.mark.parametrize("d,codes,table,kvec", [
+    (3, [1, 2, 3, 4, 5, 6, 8, 9, 1009, 16, 18], "tab_e4e6e8_tuning_6_3d", (1, 2, 3)),
+    (3, [1, 2, 3, 4, 5, 6, 8, 9, 1009, 16, 18], "tab_e4e6e8_tuning_6_3d", (0, 0, 5)),
+    (2, [1, 2, 4, 5, 8, 9, 18], "tab_e4e6e8_tuning_6_2d", (3, 2)),
+])
+def test_force_plane_wave_exact(d, codes, table, kvec):
+    """eq. (sc_f) for a plane wave of psi, psi(x) = a + b sin(k.x): by the +-symmetry of every
+    shell, sum_e W psi(x + e) e = b cos(k.x) sum_e W sin(k.e) e exactly, for any stencil.
+    The density is chosen so that psi = exp(-1/n) is that wave; the sum over the stencil is
+    done here by brute force over the integer vectors of each shell's symmetry group (in 3D,
+    9 is the (2,2,1) group, 1009 the (3,0,0) group and 18 the (3,3,0) group). Pins the reach-4 shells of the
+    Tolman-length tuning tables in 2D and 3D, along an axis and an oblique direction."""
+    from itertools import product
+    rows = GOLD[table]["d3" if d == 3 else "d2"]
+    W = table_weights(rows, s0=Fr(-2, 5), s1=Fr(1, 7), d0=Fr(3, 10))
+    Wl = [float(W[c]) for c in codes]
+    dims = (12, 10, 14)[:d]
+    k = np.array([2 * np.pi * m / L for m, L in zip(kvec, dims)])
+    a, b, G = 0.5, 0.1, -7.0
+    grid = np.stack(np.meshgrid(*[np.arange(L) for L in dims], indexing="ij"), axis=-1)  # [x][y](z)
+    phase = grid @ k
+    psi = a + b * np.sin(phase)
+    n = -1.0 / np.log(psi)
+    n0 = np.transpose(n).reshape(-1)  # x fastest
+    s = oracle.Sim(dims, 1.0, G, codes, Wl).init_density(n0)
+    F = s.fields()["F"][:, :d]
+    # symmetry groups by their sorted absolute components (2D: third component 0)
+    groups = {1: [0, 0, 1], 2: [0, 1, 1], 3: [1, 1, 1], 4: [0, 0, 2], 5: [0, 1, 2], 6: [1, 1, 2],
+              8: [0, 2, 2], 9: [1, 2, 2] if d == 3 else [0, 0, 3], 1009: [0, 0, 3], 16: [0, 0, 4],
+              18: [0, 3, 3]}
+    acc = np.zeros(d)
+    for e in product(range(-4, 5), repeat=d):
+        e = np.array(e)
+        srt = sorted(np.abs(np.concatenate([e, np.zeros(3 - d, int)])).tolist())
+        for c, w in zip(codes, Wl):
+            if srt == groups[c]:
+                acc += w * np.sin(k @ e) * e
+    psi_flat = np.transpose(psi).reshape(-1)
+    cos_flat = np.transpose(np.cos(phase)).reshape(-1)
+    ref = -G * CS2 * (psi_flat * b * cos_flat)[:, None] * acc[None, :]
+    assert np.abs(F - ref).max() < 1e-13 * np.abs(ref).max()
+
+
 @pytest.mark.slow
 def test_flat_interface_mechanical_equilibrium():
     """App. LPT d=2 / Sec. Interface Physics: at a converged flat interface the normal

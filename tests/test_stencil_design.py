@@ -78,3 +78,53 @@ def test_moments_of_maximally_isotropic_e8():
     assert abs(m["e2"] - 1) < 1e-15 and abs(m["e4"] - 4 / 7) < 1e-15 and abs(m["e8"] - 16 / 105) < 1e-15
     for k in ("I40", "I60", "I80", "I81"):
         assert abs(m[k]) < 1e-14, k
+
+
+@pytest.mark.parametrize("s0,s1,d0", KNOBS)
+def test_tolman_stencil_3d_matches_paper_table(s0, s1, d0):
+    """The product's 3D solver reproduces Table tab:e4e6e8_tuning_6_3d (11 shells, d = 3) from
+    the same knob relations, and the weights satisfy the paper's 3D isotropy conditions
+    I_4,0 ... I_8,2 (Appendix "Defining the stencil", evaluated by the oracle's exact algebra)."""
+    tab = _table(GOLD["tab_e4e6e8_tuning_6_3d"]["d3"], s0=s0, s1=s1, d0=d0)
+    W = stencil.tolman_stencil_3d(s0, s1, d0)
+    for c, w in zip(stencil.TOLMAN_SHELLS_3D, W):
+        assert abs(w - tab[c]) < 1e-12 * max(1.0, abs(tab[c])), c
+    co = sa.coefficients(3, {c: Fr(float(w)) for c, w in zip(stencil.TOLMAN_SHELLS_3D, W)})
+    assert abs(float(co["e2"]) - 1.0) < 1e-13
+    for k in ("I40", "I60", "I61", "I80", "I81", "I82"):
+        assert abs(float(co[k])) < 1e-10, k
+    assert abs(-float(co["e4"]) / 2 - s0) < 1e-13
+
+
+def test_shell_vectors_3d_group_sizes():
+    sizes = {1: 6, 2: 12, 3: 8, 4: 6, 5: 24, 6: 24, 8: 12, 9: 24, 1009: 6, 16: 6, 18: 12}
+    for c, n in sizes.items():
+        assert len(stencil.shell_vectors_3d(c)) == n, c
+
+
+def _line_projection(vectors_of, codes, W):
+    """W1(k) = sum of W over the stencil vectors with e_x = k, k = 1..4: the weights a profile
+    varying along x alone sees."""
+    out = np.zeros(4)
+    for c, w in zip(codes, W):
+        for v in vectors_of(c):
+            if v[0] > 0:
+                out[v[0] - 1] += w
+    return out
+
+
+def test_line_projection_of_tuning_tables():
+    """The 2D Tolman table projects on a line to weights reaching 3 sites, fixed by e_2, e_4,
+    e_6 alone: changing delta_0 leaves a flat profile (and its bulk densities) exactly
+    unchanged, as the paper reports for flat interfaces. The 3D table's projection reaches 4
+    sites ((3,0,0) and (4,0,0) groups) and does follow delta_0."""
+    e4 = 0.8
+    s0, s1 = -e4 / 2, e4 ** 1.5 / 4
+    d0 = 1 / 12 + 95 * e4 / 432 + 7 * e4 ** 1.5 / 72 - 5 * e4 ** 2 / 144
+    p2 = [_line_projection(stencil.shell_vectors_2d, stencil.TOLMAN_SHELLS_2D, stencil.tolman_stencil_2d(s0, s1, d0 * (1 + dd)))
+          for dd in (-0.2, 0.0, 0.2)]
+    assert p2[1][3] == 0.0
+    assert np.abs(p2[0] - p2[1]).max() < 1e-14 and np.abs(p2[2] - p2[1]).max() < 1e-14
+    p3 = [_line_projection(stencil.shell_vectors_3d, stencil.TOLMAN_SHELLS_3D, stencil.tolman_stencil_3d(s0, s1, d0 * (1 + dd)))
+          for dd in (-0.2, 0.0, 0.2)]
+    assert abs(p3[2][3] - p3[1][3]) > 1e-4
