@@ -67,15 +67,16 @@ template <class S, class M, int CPL> __device__ __forceinline__ void stv(S* p, c
 // nx values. The descriptor r starts one value before the row (so every offset is
 // non-negative) and spans nx + 1 values. Without WRAP the positions lie inside the row: the
 // lane's byte offset xb = xw * sizeof(S) plus the constant (dx + 1) * sizeof(S). With WRAP
-// (strips at the periodic seam) each value's position is wrapped on its own.
+// (strips at the periodic seam) each value's position is wrapped on its own; the wrapped
+// offsets wo[dx + 1][c] are fixed for the whole march and computed once. sel is 0, or an
+// offset past the buffer's end for rows with nothing to load.
 template <class S, class M, int CPL, bool WRAP>
-__device__ __forceinline__ void ld_row(Rsrc r, uint32_t xb, int xw, int nx, int dx, bool active, M* out) {
+__device__ __forceinline__ void ld_row(Rsrc r, uint32_t xb, const uint32_t (*wo)[CPL], int dx, uint32_t sel, M* out) {
   if constexpr (!WRAP) {
-    ldb<S, M, CPL>(r, xb + (uint32_t)((dx + 1) * (int)sizeof(S)), out);
+    ldb<S, M, CPL>(r, (xb | sel) + (uint32_t)((dx + 1) * (int)sizeof(S)), out);
   } else {
 #pragma unroll
-    for (int c = 0; c < CPL; ++c)
-      ldb<S, M, 1>(r, active ? (uint32_t)(wrapi(xw + c + dx, nx) + 1) * sizeof(S) : 0x80000000u, out + c);
+    for (int c = 0; c < CPL; ++c) ldb<S, M, 1>(r, wo[dx + 1][c] | sel, out + c);
   }
 }
 
@@ -160,6 +161,17 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
   const bool seam = it.x0 - HX - 1 < 0 || it.x0 + CPL * NO + HX + 1 > nx;
   auto march = [&](auto SEAM) {
     constexpr bool WRAP = decltype(SEAM)::value;
+    // wrapped byte offsets of the lane's values (and its halo group's) at x + dx, dx = a - 1
+    uint32_t wo[3][CPL], who[3][CPL];
+    if constexpr (WRAP) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+          wo[a][c] = need ? (uint32_t)(wrapi(xw + c + a - 1, nx) + 1) * sizeof(S) : OFF;
+          who[a][c] = needh ? (uint32_t)(wrapi(xwh + c + a - 1, nx) + 1) * sizeof(S) : OFF;
+        }
+    }
     // fr: populations of the rows between their load and their collision (R + 1 rows) plus
     // the row whose loads are in flight; hr: the same for the halo group (current + next).
     M fr[NSLOT][Q][CPL];
@@ -182,8 +194,8 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         const Rsrc rs = mkrsrc(fb + (long long)i * cells + rowo[1 - V::cy(i)] - 1, rowbytes);
-        ld_row<S, M, CPL, WRAP>(rs, xb | rowoff, xw, nx, -V::cx(i), need && k < total, fr[j % NSLOT][i]);
-        ld_row<S, M, CPL, WRAP>(rs, xbh | rowoff, xwh, nx, -V::cx(i), needh && k < total, hr[j % (PF + 1)][i]);
+        ld_row<S, M, CPL, WRAP>(rs, xb, wo, -V::cx(i), rowoff, fr[j % NSLOT][i]);
+        ld_row<S, M, CPL, WRAP>(rs, xbh, who, -V::cx(i), rowoff, hr[j % (PF + 1)][i]);
       }
     };
 
