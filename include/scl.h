@@ -207,11 +207,13 @@ scl_status scl_flat_observables(scl_lattice lat, const double* bulk, double* out
  *       marches (>= 1; 0 = automatic: 64 for FP16 storage, 32 otherwise); cpl = sites per lane
  *       (1, or 2 for vector accesses, which needs every domain width even and a strip of at
  *       most 256; 0 = automatic: one site per lane).
- *   3D: strip = tile index (1: 64x4, 2: 64x8, 3: 32x8 output sites per workgroup);
- *       seg = planes one workgroup marches; cpl is ignored.
+ *   3D: strip = tile index (1: 64x4, 2: 64x8, 3: 32x8 output sites per workgroup;
+ *       automatic until set: 64x4 for FP16 storage, 64x8 otherwise and for the reach-4
+ *       set); seg = planes one workgroup marches; cpl is ignored.
  * 0 keeps the current value (for cpl: automatic). */
 scl_status scl_set_tiling(scl_lattice lat, int32_t strip, int32_t seg, int32_t cpl);
-/* Current tiling (2D: the strip in use); cpl may be NULL. seg 0 means the automatic choice. */
+/* Current tiling (2D: the strip in use, 3D: the tile in use); cpl may be NULL. seg 0 means the
+ * automatic choice. */
 scl_status scl_get_tiling(scl_lattice lat, int32_t* strip, int32_t* seg, int32_t* cpl);
 
 /* Autotuner: times the candidate tilings on this lattice (advancing it by the steps it

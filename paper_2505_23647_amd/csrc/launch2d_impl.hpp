@@ -1,0 +1,39 @@
+// Body of the 2D step launcher; each k2d_*.hip instantiates it for one storage precision.
+#pragma once
+#include <type_traits>
+
+#include "launch.hpp"
+#include "step2d.hpp"
+
+namespace scl {
+
+template <class S, class M, bool SHIFT>
+hipError_t launch_step2d(const StepArgs& a, const void* fin, void* fout, MacroRec<M> rec, bool record) {
+  // eight XCDs: the kernel maps workgroup id -> item so that each XCD takes a contiguous
+  // eighth of the list; round the grid up to a multiple of 8
+  const int per = (a.nitems + 7) / 8;
+  const dim3 grid(8 * per);
+#define SCL_2D_CASE(SETV, NOV, CPLV)                                                                  \
+  if (a.set == SETV && a.strip == NOV && a.cpl == CPLV) {                                              \
+    if constexpr (!std::is_same<S, _Float16>::value) {                                                 \
+      if (record) {                                                                                    \
+        hipLaunchKernelGGL((k_step2d<S, M, SETV, NOV, CPLV, SHIFT, true>), grid, dim3(NOV), 0, a.stream, \
+                           (const S*)fin, (S*)fout, a.doms, a.items, a.nitems, rec);                   \
+        return hipGetLastError();                                                                      \
+      }                                                                                                \
+    }                                                                                                  \
+    hipLaunchKernelGGL((k_step2d<S, M, SETV, NOV, CPLV, SHIFT, false>), grid, dim3(NOV), 0, a.stream,  \
+                       (const S*)fin, (S*)fout, a.doms, a.items, a.nitems, rec);                       \
+    return hipGetLastError();                                                                          \
+  }
+  SCL_2D_CASE(0, 64, 1) SCL_2D_CASE(0, 128, 1) SCL_2D_CASE(0, 256, 1)
+  SCL_2D_CASE(1, 64, 1) SCL_2D_CASE(1, 128, 1) SCL_2D_CASE(1, 256, 1)
+  SCL_2D_CASE(0, 64, 2) SCL_2D_CASE(0, 128, 2) SCL_2D_CASE(0, 256, 2)
+  SCL_2D_CASE(1, 64, 2) SCL_2D_CASE(1, 128, 2) SCL_2D_CASE(1, 256, 2)
+  SCL_2D_CASE(2, 128, 1) SCL_2D_CASE(2, 256, 1)
+  SCL_2D_CASE(0, 512, 1) SCL_2D_CASE(1, 512, 1)
+#undef SCL_2D_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace scl

@@ -15,7 +15,7 @@
 
 #include "scl.h"
 #include "scl_common.hpp"
-#include "step2d.hpp"
+#include "launch.hpp"
 #include "step3d.hpp"
 #include "readout.hpp"
 #include "adjoint.hpp"
@@ -96,7 +96,8 @@ struct scl_lattice_s {
   int strip_eff = 256;             // 2D: output lanes per workgroup in use
   int cpl_req = 0;                 // 2D: sites per lane requested (0 = auto)
   int cpl = 1;                     // 2D: sites per lane in use
-  int tile3 = 2, seg3 = 0;         // 3D: tile index, planes per item (0 = auto)
+  int tile3 = 0, seg3 = 0;         // 3D: tile index, planes per item (0 = auto)
+  int tile3_eff = 2;               // 3D: tile index in use
   // graphs
   int graph_k = 0;
   hipGraphExec_t gexec = nullptr;
@@ -217,7 +218,10 @@ scl_status build_items(scl_lattice_s* L) {
           }
     }
   } else {
-    const Tile3 t = TILES3[L->tile3];
+    // automatic tile: measured best on MI355X (512^3, 92 vectors): 64x8 for 4- and 8-byte
+    // storage, 64x4 for FP16 storage (9% faster there); 64x8 for the reach-4 set
+    L->tile3_eff = L->tile3 ? L->tile3 : (L->prec == SCL_FP16S_FP32 && L->set != 2 ? 1 : 2);
+    const Tile3 t = TILES3[L->tile3_eff];
     const int ox = t.tx, oy = t.ty;
     int seg = L->seg3;
     if (seg <= 0) {
@@ -270,80 +274,44 @@ void drop_graph(scl_lattice_s* L) {
 }
 
 // ------------------------------------------------------------------ step dispatch
-template <class S, class M, bool SHIFT>
-hipError_t launch2d(scl_lattice_s* L, const void* fin, void* fout, MacroRec<M> rec, bool record) {
-  // eight XCDs: the kernel maps workgroup id -> item so that each XCD takes a contiguous
-  // eighth of the list; round the grid up to a multiple of 8
-  const int per = (L->nitems + 7) / 8;
-  const dim3 grid(8 * per);
-#define SCL_2D_CASE(SETV, NOV, CPLV)                                                                  \
-  if (L->set == SETV && L->strip_eff == NOV && L->cpl == CPLV) {                                       \
-    constexpr int nt = NOV;                                                                            \
-    if constexpr (!std::is_same<S, _Float16>::value) {                                                 \
-      if (record) {                                                                                    \
-        hipLaunchKernelGGL((k_step2d<S, M, SETV, NOV, CPLV, SHIFT, true>), grid, dim3(nt), 0, L->launch, \
-                           (const S*)fin, (S*)fout, L->d_doms, L->d_items, L->nitems, rec);            \
-        return hipGetLastError();                                                                      \
-      }                                                                                                \
-    }                                                                                                  \
-      hipLaunchKernelGGL((k_step2d<S, M, SETV, NOV, CPLV, SHIFT, false>), grid, dim3(nt), 0, L->launch, \
-                         (const S*)fin, (S*)fout, L->d_doms, L->d_items, L->nitems, rec);              \
-    return hipGetLastError();                                                                          \
-  }
-  SCL_2D_CASE(0, 64, 1) SCL_2D_CASE(0, 128, 1) SCL_2D_CASE(0, 256, 1)
-  SCL_2D_CASE(1, 64, 1) SCL_2D_CASE(1, 128, 1) SCL_2D_CASE(1, 256, 1)
-  SCL_2D_CASE(0, 64, 2) SCL_2D_CASE(0, 128, 2) SCL_2D_CASE(0, 256, 2)
-  SCL_2D_CASE(1, 64, 2) SCL_2D_CASE(1, 128, 2) SCL_2D_CASE(1, 256, 2)
-  SCL_2D_CASE(2, 128, 1) SCL_2D_CASE(2, 256, 1)
-  SCL_2D_CASE(0, 512, 1) SCL_2D_CASE(1, 512, 1)
-#undef SCL_2D_CASE
-  return hipErrorInvalidValue;
-}
-
-template <class S, class M, bool SHIFT>
-hipError_t launch3d(scl_lattice_s* L, const void* fin, void* fout) {
-  // pass 1: psi of every site, domain by domain
-  for (int k = 0; k < L->ndom; ++k) {
-    const DomDev& dd = L->h_doms[k];
-    hipLaunchKernelGGL((k_psi3d<S, M, SHIFT>), dim3((L->nx[k] + 255) / 256, L->ny[k], L->nz[k]), dim3(256), 0,
-                       L->launch, (const S*)fin, (M*)L->d_psi3, dd);
-  }
-  // pass 2: force, collision, streaming over the work items
-  const int per = (L->nitems + 7) / 8;
-  const dim3 grid(8 * per);
-#define SCL_3D_CASE(SETV, TI, TXV, TYV)                                                          \
-  if (L->set == SETV && L->tile3 == TI) {                                                          \
-    hipLaunchKernelGGL((k_step3d<S, M, SETV, TXV, TYV, SHIFT>), grid, dim3(TXV * TYV), 0, L->launch, \
-                       (const S*)fin, (S*)fout, (const M*)L->d_psi3, L->d_doms, L->d_items, L->nitems); \
-    return hipGetLastError();                                                                     \
-  }
-  SCL_3D_CASE(0, 1, 64, 4) SCL_3D_CASE(0, 2, 64, 8) SCL_3D_CASE(0, 3, 32, 8)
-  SCL_3D_CASE(1, 1, 64, 4) SCL_3D_CASE(1, 2, 64, 8) SCL_3D_CASE(1, 3, 32, 8)
-  SCL_3D_CASE(2, 2, 64, 8) SCL_3D_CASE(2, 3, 32, 8)
-#undef SCL_3D_CASE
-  return hipErrorInvalidValue;
+// The launchers live in k2d_*.hip / k3d_*.hip, one translation unit per storage precision.
+StepArgs step_args(const scl_lattice_s* L) {
+  StepArgs a{};
+  a.set = L->set;
+  a.strip = L->strip_eff;
+  a.cpl = L->cpl;
+  a.tile3 = L->tile3_eff;
+  a.nitems = L->nitems;
+  a.doms = L->d_doms;
+  a.items = L->d_items;
+  a.stream = L->launch;
+  a.ndom = L->ndom;
+  a.hdoms = L->h_doms.data();
+  a.psi = L->d_psi3;
+  return a;
 }
 
 // One step from A into B (no swap).
 hipError_t launch_step(scl_lattice_s* L, const void* fin, void* fout, const MacroRec<double>* rec64,
                        const MacroRec<float>* rec32) {
+  const StepArgs a = step_args(L);
   if (L->d == 2) {
     switch (L->prec) {
       case SCL_FP64:
-        return launch2d<double, double, false>(L, fin, fout, rec64 ? *rec64 : MacroRec<double>{}, rec64 != nullptr);
+        return launch_step2d<double, double, false>(a, fin, fout, rec64 ? *rec64 : MacroRec<double>{}, rec64 != nullptr);
       case SCL_FP32:
-        return launch2d<float, float, false>(L, fin, fout, rec32 ? *rec32 : MacroRec<float>{}, rec32 != nullptr);
+        return launch_step2d<float, float, false>(a, fin, fout, rec32 ? *rec32 : MacroRec<float>{}, rec32 != nullptr);
       case SCL_FP32_SHIFTED:
-        return launch2d<float, float, true>(L, fin, fout, rec32 ? *rec32 : MacroRec<float>{}, rec32 != nullptr);
+        return launch_step2d<float, float, true>(a, fin, fout, rec32 ? *rec32 : MacroRec<float>{}, rec32 != nullptr);
       case SCL_FP16S_FP32:
-        return launch2d<_Float16, float, true>(L, fin, fout, MacroRec<float>{}, false);
+        return launch_step2d<_Float16, float, true>(a, fin, fout, MacroRec<float>{}, false);
     }
   } else {
     switch (L->prec) {
-      case SCL_FP64: return launch3d<double, double, false>(L, fin, fout);
-      case SCL_FP32: return launch3d<float, float, false>(L, fin, fout);
-      case SCL_FP32_SHIFTED: return launch3d<float, float, true>(L, fin, fout);
-      case SCL_FP16S_FP32: return launch3d<_Float16, float, true>(L, fin, fout);
+      case SCL_FP64: return launch_step3d<double, double, false>(a, fin, fout);
+      case SCL_FP32: return launch_step3d<float, float, false>(a, fin, fout);
+      case SCL_FP32_SHIFTED: return launch_step3d<float, float, true>(a, fin, fout);
+      case SCL_FP16S_FP32: return launch_step3d<_Float16, float, true>(a, fin, fout);
     }
   }
   return hipErrorInvalidValue;
@@ -1152,11 +1120,11 @@ scl_status scl_set_tiling(scl_lattice L, int32_t strip, int32_t seg, int32_t cpl
 
 scl_status scl_get_tiling(scl_lattice L, int32_t* strip, int32_t* seg, int32_t* cpl) {
   if (!L || !strip || !seg) return fail(SCL_E_INVALID, "bad arguments");
-  if (L->d == 2 && L->dirty_items) {
+  if (L->dirty_items) {
     scl_status st = build_items(L);
     if (st != SCL_OK) return st;
   }
-  *strip = L->d == 2 ? L->strip_eff : L->tile3;
+  *strip = L->d == 2 ? L->strip_eff : L->tile3_eff;
   *seg = L->d == 2 ? L->seg : L->seg3;
   if (cpl) *cpl = L->d == 2 ? L->cpl : 1;
   return SCL_OK;

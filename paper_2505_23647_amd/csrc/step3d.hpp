@@ -8,6 +8,16 @@
 
 
 
+// minimum waves per SIMD the 3D step is compiled for (0: no bound beyond the block size)
+#ifndef SCL_STEP3D_WPE
+#define SCL_STEP3D_WPE 0
+#endif
+#if SCL_STEP3D_WPE > 0
+#define SCL_STEP3D_ATTR __attribute__((amdgpu_waves_per_eu(SCL_STEP3D_WPE, SCL_STEP3D_WPE)))
+#else
+#define SCL_STEP3D_ATTR
+#endif
+
 namespace scl {
 
 // One vector of every +-pair of the 3D shell sets: the first non-zero component in the
@@ -120,7 +130,7 @@ k_psi3d(const S* __restrict__ fin, M* __restrict__ psi, DomDev dm) {
 // every lane at every step (accesses with nothing to do carry an offset past the buffer's
 // end), so that the compiler keeps the next plane's loads in flight.
 template <class S, class M, int SET, int TX, int TY, bool SHIFT>
-__global__ void __launch_bounds__(TX * TY)
+__global__ void __launch_bounds__(TX * TY) SCL_STEP3D_ATTR
 k_step3d(const S* __restrict__ fin, S* __restrict__ fout, const M* __restrict__ psi,
          const DomDev* __restrict__ doms, const WorkItem* __restrict__ items, int nitems) {
   using V = Vel<1>;
