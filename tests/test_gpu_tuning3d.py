@@ -136,3 +136,24 @@ def test_flat_tolman_length_tuning_3d():
     assert abs((d[0.2] - d[0.0]) / (d[0.0] - d[-0.2]) - 1.0) < 0.01
     assert 1.0 < slope < 1.35
     assert max(abs(sig[dd] / sig[0.0] - 1.0) for dd in (-0.2, 0.2)) < 1e-2
+
+
+@pytest.mark.parametrize("tile", [2, 3])
+def test_reach4_3d_tiny_and_batched_domains_fp64(tile):
+    """Domains smaller than the 4-site reach (the rim wraps onto the domain several times) and
+    two uneven domains in one launch, against the oracle domain by domain."""
+    say(f"case: 3D reach-4 tiny + batched domains fp64, tile {tile}")
+    G, ng, nl = _physics(0.1)
+    W = _weights(0.05)
+    dims = [(7, 5, 4), (3, 9, 6), (26, 11, 13)]
+    n0s = [synth.around(d, 0.5 * (nl + ng), 1e-2, seed=70 + k) for k, d in enumerate(dims)]
+    lat = Lattice(dims, SCL_FP64).set_physics(1.0, G, 1, EPS).set_stencil(SH, W)
+    lat.set_tiling(tile, 3)
+    lat.init_density(np.concatenate(n0s))
+    lat.step(25)
+    perm = perm_to_oracle(lat.xi, 3)
+    for k, d in enumerate(dims):
+        ora = _oracle(d, G, W, n0s[k], 25)
+        e = rel_err(lat.domain_populations(k)[perm], ora.f)
+        say(f"  domain {d}: populations rel err {e:.2e}")
+        assert e <= 1e-12
