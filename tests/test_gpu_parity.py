@@ -208,6 +208,12 @@ def test_d3q19_fp32_error():
         e = rel_err(lat.density(), ora.fields()["n"])
         say(f"  tile {tile}: {e:.2e}")
         assert e < 1e-5
+    # FP16 storage (shifted), automatic tile (64x4) and 64x8
+    for tiling in (None, (2, 9)):
+        lat = gpu_run([dims], SCL_FP16S_FP32, 0.8, G, [1, 2, 3, 4, 5, 6, 8], W, n0, 50, tiling=tiling)
+        e = rel_err(lat.density(), ora.fields()["n"])
+        say(f"  fp16 storage, tiling {tiling} (in use {lat.get_tiling()}): {e:.2e}")
+        assert e < 2e-3
 
 
 def test_full_size_c2_sampled_fp64_and_fp32():
