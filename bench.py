@@ -126,6 +126,11 @@ def batched_leg(stream, steps=2000):
     ach = 2 * 9 * 4 * lat.cells / (ms / 1e3 / steps) / 1e9
     out = {"domains": len(dims), "sites": lat.cells, "steps": steps, "MLUPS": round(ml, 1),
            "achieved_GBs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4), "tiling": list(lat.get_tiling())}
+    # the autotuner's pick for this batch (timed on the lattice itself, outside the timed run)
+    lat.tune()
+    lat.step(100)
+    ms = lat.step_timed(steps)
+    out["tuned"] = {"MLUPS": round(lat.cells * steps / (ms / 1e3) / 1e6, 1), "tiling": list(lat.get_tiling())}
     lat.close()
     return out
 
