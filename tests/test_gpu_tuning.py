@@ -131,3 +131,59 @@ def test_flat_tolman_length_tuning():
     assert abs((d[0.2] - d[0.0]) / (d[0.0] - d[-0.2]) - 1.0) < 0.01
     assert 0.9 < slope < 1.3
     assert max(abs(sig[dd] / sig[0.0] - 1.0) for dd in (-0.2, 0.2)) < 1e-2
+
+
+def test_closed_interface_tolman_tuning_2d():
+    """Sec. "Higher-order Tolman length tuning", closed interfaces in d = 2: droplets and bubbles
+    of 16 radii (12..96, side 4R + 32) with the reach-4 tuning stencil at Delta_delta in
+    (-0.2, 0, 0.2), 40000 steps in one batched launch each (FP32 shifted storage, graphs). The
+    fit of dP R_s / sigma_0 against the signed curvature (-1)^b / R_s gives the surface tension
+    (intercept) and -delta (slope). Asserted: the Laplace law holds at a fixed slope for every
+    Delta_delta and the surface tension moves by under 3%, as the paper reports. The fitted
+    delta (5.1, 5.8, 4.9 on MI355X) is not resolved well enough at these radii and this
+    relaxation time to show the knob's +-20%; only its range is checked (the flat interface
+    resolves the knob: test_flat_tolman_length_tuning)."""
+    from oracle import flat as oflat
+    from paper_2505_23647_amd import SCL_FP32_SHIFTED
+    say("case: closed-interface Tolman tuning, 2D, 32 domains x 3 knob values, 40000 steps")
+    G, ng, nl = _physics(0.1)
+    # sigma_0 of the flat interface at the reference knobs (FP64 slab)
+    lat = _lattice([(128, 1)], SCL_FP64, G, _weights(0.0), synth.slab(128, nl, ng, 32.0))
+    lat.set_graph_steps(100)
+    lat.step(60000)
+    sigma0 = lat.flat_observables()[0][0, 0]
+    lat.close()
+    radii = np.exp(np.linspace(np.log(12.0), np.log(96.0), 16))
+    dims, n0, centers, bubble = [], [], [], []
+    for k, R in enumerate(radii):
+        L = int(round(4 * R + 32))
+        for b in (0, 1):
+            n_in, n_out = (ng, nl) if b else (nl, ng)
+            dims.append((L, L))
+            n0.append(synth.droplet((L, L), R, n_in, n_out, noise=1e-3, seed=300 + 2 * k + b))
+            centers.append((L // 2, L // 2))
+            bubble.append(b)
+    n0 = np.concatenate(n0)
+    centers, bubble = np.array(centers), np.array(bubble, dtype=np.int8)
+    sgn = np.where(bubble == 1, -1.0, 1.0)
+    fits = {}
+    for dd in (-0.2, 0.0, 0.2):
+        lat = _lattice(dims, SCL_FP32_SHIFTED, G, _weights(dd), n0)
+        lat.set_graph_steps(100)
+        lat.step(40000)
+        obs = lat.droplet_observables(centers, bubble)
+        lat.close()
+        dP, Rs, Re = obs[:, 0], obs[:, 2], obs[:, 4]
+        ok = np.isfinite(Rs) & (np.repeat(radii, 2) >= 16)
+        slope, icpt = np.polyfit(sgn[ok] / Rs[ok], dP[ok] * Rs[ok] / sigma0, 1)
+        lap = dP[ok] * Re[ok] / sigma0
+        fits[dd] = (icpt, -slope)
+        say(f"  Delta_delta={dd:+.1f}: {ok.sum()} domains, intercept {icpt:.4f}, delta {-slope:.3f}, "
+            f"dP R_e / sigma_0 in {lap.min():.3f}..{lap.max():.3f}")
+        assert ok.sum() >= 20
+        assert np.all(np.abs(lap - 1.0) < 0.15)
+    d = {k: v[1] for k, v in fits.items()}
+    say(f"  sigma_0 (flat) {sigma0:.6f}; delta ratios {d[-0.2] / d[0.0]:.3f}, {d[0.2] / d[0.0]:.3f}")
+    for dd in (-0.2, 0.2):
+        assert abs(fits[dd][0] / fits[0.0][0] - 1.0) < 0.03
+    assert all(2.0 < v < 10.0 for v in d.values())
