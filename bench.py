@@ -238,7 +238,7 @@ def main():
                     help="copy: device copy for counter calibration; d3q19: the 3D leg alone")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.mode == "copy":
         copy_calibration()
