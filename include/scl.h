@@ -54,7 +54,7 @@ typedef enum {
   SCL_E_DEVICE = 3,      /* a HIP call failed; scl_last_error() holds hipGetErrorString */
   SCL_E_STATE = 4,       /* call out of order (e.g. scl_step before scl_init_density) */
   SCL_E_NONFINITE = 5,   /* a checked readout found NaN or Inf (the run diverged) */
-  SCL_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+  SCL_E_UNSUPPORTED = 6  /* valid request the library does not implement */
 } scl_status;
 
 typedef enum { SCL_D2Q9 = 0, SCL_D3Q19 = 1 } scl_velset;
