@@ -146,3 +146,31 @@ def test_flat_tolman_tuning_with_reach4_stencil():
     d = {k: v[2] for k, v in res.items()}
     assert abs((d[0.2] - d[0.0]) / (d[0.0] - d[-0.2]) - 1.0) < 0.01
     assert 0.9 < (d[0.2] - d[-0.2]) / (0.4 * d[0.0]) < 1.3
+
+
+def test_flat_tolman_tuning_with_3d_table():
+    """The same flat tuning with the 3D table (tab. e4e6e8_tuning_6_3d) on a quasi-1D slab
+    (128 x 1 x 1, every vector's transverse part wraps onto the same site): delta stays linear
+    in Delta_delta, but the table's projection on a line reaches 4 sites and follows e_8, so
+    the bulk densities move (by ~1e-4 at Delta_delta = +-0.2), unlike with the 2D table."""
+    eps, e4 = 14 / 29, 0.8
+    G = thermo.G_for_reduced_temperature(0.1, kind=1, eps=eps)
+    ng, nl, _ = thermo.coexistence(G, kind=1, eps=eps)
+    s0, s1 = -e4 / 2, e4 ** 1.5 / 4
+    d0 = 1 / 12 + 95 * e4 / 432 + 7 * e4 ** 1.5 / 72 - 5 * e4 ** 2 / 144
+    res = {}
+    for dd in (-0.2, 0.0, 0.2):
+        W = stencil.tolman_stencil_3d(s0, s1, d0 * (1 + dd))
+        s = oracle.Sim((128, 1, 1), 1.0, G, list(stencil.TOLMAN_SHELLS_3D), W, oracle.PSI_EPS, eps)
+        s.init_density(synth.slab(128, nl, ng, 32.0))
+        assert s.run(60000) == 0
+        n = s.fields()["n"]
+        P = s.pressure_tensor_general()
+        assert (P[0].max() - P[0].min()) < 1e-12 * abs(P[0].mean())
+        lo, hi = flat.halves(128)[0]
+        res[dd] = (n.max(), n.min(), flat.delta_zemzs(n, P[0], P[1], lo, hi, n.max(), n.min()))
+    d = {k: v[2] for k, v in res.items()}
+    assert abs((d[0.2] - d[0.0]) / (d[0.0] - d[-0.2]) - 1.0) < 0.01
+    for dd in (-0.2, 0.2):
+        rel = abs(res[dd][0] / res[0.0][0] - 1.0)
+        assert 1e-6 < rel < 1e-3
