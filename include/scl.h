@@ -202,18 +202,24 @@ scl_status scl_droplet_observables(scl_lattice lat, const int32_t* center, const
 scl_status scl_flat_observables(scl_lattice lat, const double* bulk, double* out);
 
 /* Tiling of the fused step.
- *   2D: strip = output lanes per workgroup (64, 128, 256 or 512; 0 = automatic: 512 for FP32
- *       storage, 256 otherwise and for the reach-4 shell set); seg = rows one workgroup
- *       marches (>= 1; 0 = automatic: 64 for FP16 storage, 32 otherwise); cpl = sites per lane
- *       (1, or 2 for vector accesses, which needs every domain width even and a strip of at
- *       most 256; 0 = automatic: one site per lane).
+ *   2D marching strips: strip = output lanes per workgroup (64, 128, 256 or 512; 0 =
+ *       automatic: 512 for FP32 storage, 256 otherwise and for the reach-4 shell set); seg =
+ *       rows one workgroup marches (>= 1; 0 = automatic: 64 for FP16 storage, 32 otherwise);
+ *       cpl = sites per lane (1, or 2 for vector accesses, which needs every domain width even
+ *       and a strip of at most 256; 0 = automatic: one site per lane).
+ *   2D one-shot tiles: strip = -256 or -512 (lanes per workgroup), seg = rows per tile (8, 16,
+ *       24 or 32; 0 = 16; 512 lanes need at least 16), cpl ignored: one workgroup per tile of
+ *       64 x seg sites, no march. Needs every domain's population plane (sites x bytes per
+ *       value) under 2 GiB (SCL_E_UNSUPPORTED otherwise). Results are bitwise those of the
+ *       marching strips. With no tiling requested, FP64 storage with the shell sets of reach 1
+ *       and 2 runs 256-lane tiles of 64 x 24 sites; scl_adjoint's recording pass always marches.
  *   3D: strip = tile index (1: 64x4, 2: 64x8, 3: 32x8 output sites per workgroup;
  *       automatic until set: 64x4 for FP16 storage, 64x8 otherwise and for the reach-4
  *       set); seg = planes one workgroup marches; cpl is ignored.
  * 0 keeps the current value (for cpl: automatic). */
 scl_status scl_set_tiling(scl_lattice lat, int32_t strip, int32_t seg, int32_t cpl);
-/* Current tiling (2D: the strip in use, 3D: the tile in use); cpl may be NULL. seg 0 means the
- * automatic choice. */
+/* Current tiling (2D: the strip in use, or -lanes with seg = rows per tile when one-shot tiles
+ * are in use; 3D: the tile in use); cpl may be NULL. seg 0 means the automatic choice. */
 scl_status scl_get_tiling(scl_lattice lat, int32_t* strip, int32_t* seg, int32_t* cpl);
 
 /* Autotuner: times the candidate tilings on this lattice (advancing it by the steps it

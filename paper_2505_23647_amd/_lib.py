@@ -73,6 +73,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_2505_23647_amd.build.build()")
+        # torch brings its own copy of the HIP runtime. Loaded first, it also serves the
+        # library; loaded after the library had initialised the system runtime, it finds no GPU.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)

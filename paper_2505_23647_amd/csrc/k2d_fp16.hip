@@ -2,4 +2,5 @@
 #include "launch2d_impl.hpp"
 namespace scl {
 template hipError_t launch_step2d<_Float16, float, true>(const StepArgs&, const void*, void*, MacroRec<float>, bool);
+template hipError_t launch_tile2d<_Float16, float, true>(const StepArgs&, const void*, void*);
 }

@@ -2,4 +2,5 @@
 #include "launch2d_impl.hpp"
 namespace scl {
 template hipError_t launch_step2d<float, float, false>(const StepArgs&, const void*, void*, MacroRec<float>, bool);
+template hipError_t launch_tile2d<float, float, false>(const StepArgs&, const void*, void*);
 }

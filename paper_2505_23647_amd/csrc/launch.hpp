@@ -11,6 +11,8 @@ namespace scl {
 struct StepArgs {
   int set;        // compile-time shell set index
   int strip;      // 2D: output lanes per workgroup in use
+  int tile2;      // 2D: 0 = marching strips; 256 or 512 = one-shot 64 x tile_ty tiles, that many lanes
+  int tile_ty;    // 2D tiles: rows per tile
   int cpl;        // 2D: sites per lane
   int tile3;      // 3D: tile index in use (1: 64x4, 2: 64x8, 3: 32x8)
   int nitems;
@@ -26,6 +28,9 @@ struct StepArgs {
 // One 2D step from fin into fout; rec: record n, j, F of every site (adjoint recomputation).
 template <class S, class M, bool SHIFT>
 hipError_t launch_step2d(const StepArgs& a, const void* fin, void* fout, MacroRec<M> rec, bool record);
+// One 2D step over one-shot tiles (no recording).
+template <class S, class M, bool SHIFT>
+hipError_t launch_tile2d(const StepArgs& a, const void* fin, void* fout);
 // One 3D step (psi pass, then the fused pass) from fin into fout.
 template <class S, class M, bool SHIFT>
 hipError_t launch_step3d(const StepArgs& a, const void* fin, void* fout);
