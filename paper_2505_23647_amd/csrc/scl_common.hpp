@@ -270,22 +270,24 @@ __device__ __forceinline__ Rsrc mkrsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
 
-// CPL stored values at byte offset voff of the buffer r, converted to M.
-template <class S, class M, int CPL> __device__ __forceinline__ void ldb(Rsrc r, uint32_t voff, M* out) {
+// CPL stored values at byte offset voff + soff of the buffer r (soff: a uniform offset),
+// converted to M. A voff at or past the buffer's size drops the access.
+template <class S, class M, int CPL>
+__device__ __forceinline__ void ldb(Rsrc r, uint32_t voff, M* out, uint32_t soff = 0) {
   constexpr int B = (int)sizeof(S) * CPL;
   S t[CPL];
   if constexpr (B == 2) {
-    const auto u = __builtin_amdgcn_raw_buffer_load_b16(r, voff, 0, 0);
+    const auto u = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
     __builtin_memcpy(t, &u, B);
   } else if constexpr (B == 4) {
-    const auto u = __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0);
+    const auto u = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
     __builtin_memcpy(t, &u, B);
   } else if constexpr (B == 8) {
-    const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0);
+    const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
     __builtin_memcpy(t, &u, B);
   } else {
     static_assert(B == 16, "unsupported access width");
-    const auto u = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
+    const auto u = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
     __builtin_memcpy(t, &u, B);
   }
 #pragma unroll
@@ -293,7 +295,7 @@ template <class S, class M, int CPL> __device__ __forceinline__ void ldb(Rsrc r,
 }
 
 template <class S, class M, int CPL, int AUX = 0>
-__device__ __forceinline__ void stb(Rsrc r, uint32_t voff, const M* in) {
+__device__ __forceinline__ void stb(Rsrc r, uint32_t voff, const M* in, uint32_t soff = 0) {
   constexpr int B = (int)sizeof(S) * CPL;
   S t[CPL];
 #pragma unroll
@@ -301,19 +303,19 @@ __device__ __forceinline__ void stb(Rsrc r, uint32_t voff, const M* in) {
   if constexpr (B == 2) {
     unsigned short u;
     __builtin_memcpy(&u, t, B);
-    __builtin_amdgcn_raw_buffer_store_b16(u, r, voff, 0, AUX);
+    __builtin_amdgcn_raw_buffer_store_b16(u, r, voff, soff, AUX);
   } else if constexpr (B == 4) {
     uint32_t u;
     __builtin_memcpy(&u, t, B);
-    __builtin_amdgcn_raw_buffer_store_b32(u, r, voff, 0, AUX);
+    __builtin_amdgcn_raw_buffer_store_b32(u, r, voff, soff, AUX);
   } else if constexpr (B == 8) {
     uint32_t u __attribute__((ext_vector_type(2)));
     __builtin_memcpy(&u, t, B);
-    __builtin_amdgcn_raw_buffer_store_b64(u, r, voff, 0, AUX);
+    __builtin_amdgcn_raw_buffer_store_b64(u, r, voff, soff, AUX);
   } else {
     uint32_t u __attribute__((ext_vector_type(4)));
     __builtin_memcpy(&u, t, B);
-    __builtin_amdgcn_raw_buffer_store_b128(u, r, voff, 0, AUX);
+    __builtin_amdgcn_raw_buffer_store_b128(u, r, voff, soff, AUX);
   }
 }
 

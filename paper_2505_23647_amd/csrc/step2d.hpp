@@ -71,14 +71,17 @@ template <class S, class M, int CPL> __device__ __forceinline__ void stv(S* p, c
 // offsets wo[dx + 1][c] are fixed for the whole march and computed once. sel is 0, or an
 // offset past the buffer's end for rows with nothing to load.
 template <class S, class M, int CPL, bool WRAP>
-__device__ __forceinline__ void ld_row(Rsrc r, uint32_t xb, const uint32_t (*wo)[CPL], int dx, uint32_t sel, M* out) {
+__device__ __forceinline__ void ld_row(Rsrc r, uint32_t xb, const uint32_t (*wo)[CPL], int dx, uint32_t sel, M* out,
+                                       uint32_t soff) {
   if constexpr (!WRAP) {
-    ldb<S, M, CPL>(r, (xb | sel) + (uint32_t)((dx + 1) * (int)sizeof(S)), out);
+    ldb<S, M, CPL>(r, (xb | sel) + (uint32_t)((dx + 1) * (int)sizeof(S)), out, soff);
   } else {
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) ldb<S, M, 1>(r, wo[dx + 1][c] | sel, out + c);
+    for (int c = 0; c < CPL; ++c) ldb<S, M, 1>(r, wo[dx + 1][c] | sel, out + c, soff);
   }
 }
+
+__host__ __device__ constexpr int ceil_pow2(int v) { return v <= 1 ? 1 : 2 * ceil_pow2((v + 1) / 2); }
 
 // Halo geometry: HX = R rounded up to CPL halo columns on each side of a strip, covered by
 // HL = HX / CPL halo lanes per side.
@@ -98,7 +101,7 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
   constexpr int R = SH::R;
   constexpr int HX = Halo2<SET, CPL>::HX;
   constexpr int HL = Halo2<SET, CPL>::HL;
-  constexpr int RING = 2 * R + 2;
+  constexpr int RING = ceil_pow2(2 * R + 2);  // psi rows kept (at least 2R + 2; a power of two)
   // rows in registers: R + 1 waiting for their collision + PF whose loads are in flight; the
   // unrolled loop cycles through NSLOT register sets (a multiple of PF + 1, the halo's sets)
   constexpr int PF = SCL_STEP2D_PF;
@@ -155,12 +158,22 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
   const int total = (it.y1 - it.y0) + 2 * R;  // marching steps: rows loaded
   const int steps = (total + NSLOT - 1) / NSLOT * NSLOT;
   const int rstart = dir > 0 ? it.y0 - R : it.y1 - 1 + R;
-  const int rbase = it.y0 - R - RING - NSLOT;  // ring row of row r: (r - rbase) % RING
+  const int rbase = it.y0 - R - RING - NSLOT;  // ring row of row r: (r - rbase) mod RING
   // Strips whose pulls never cross the periodic seam in x (all but the first and last of a
   // domain) take a branch-free path; the others resolve the seam per lane.
   const bool seam = it.x0 - HX - 1 < 0 || it.x0 + CPL * NO + HX + 1 > nx;
-  auto march = [&](auto SEAM) {
+  // Addressing. WHOLE (a domain's state under 2 GiB): one buffer descriptor spans the whole
+  // input state (from one value before it) and one the output; the plane and row of an access
+  // go into the instruction's scalar offset, so a row costs a few scalar adds. Otherwise every
+  // row of every plane gets a descriptor of its own.
+  const uint32_t planeb = (uint32_t)(cells * (long long)sizeof(S));
+  const uint32_t rowb = (uint32_t)nx * sizeof(S);
+  const bool whole = (long long)Q * cells * (long long)sizeof(S) + (long long)sizeof(S) <= 0x7fffffffLL;
+  const Rsrc rin = mkrsrc(fb - 1, (uint32_t)(Q * planeb + sizeof(S)));
+  const Rsrc rout = mkrsrc(ob, (uint32_t)(Q * planeb));
+  auto march = [&](auto SEAM, auto WH) {
     constexpr bool WRAP = decltype(SEAM)::value;
+    constexpr bool WHOLE = decltype(WH)::value;
     // wrapped byte offsets of the lane's values (and its halo group's) at x + dx, dx = a - 1
     uint32_t wo[3][CPL], who[3][CPL];
     if constexpr (WRAP) {
@@ -183,24 +196,45 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
 #pragma unroll
         for (int c = 0; c < CPL; ++c) fr[a][i][c] = M(0);
 
+    // Wrapped row of the next load and of the next collision, advanced by one row per marching
+    // step (no division in the loop).
+    auto advance = [&](int a) {
+      const int t = a + dir;
+      return t == ny ? 0 : (t < 0 ? ny - 1 : t);
+    };
+    int rw_load = wrapi(rstart, ny);
+    int rw_coll = wrapi(rstart - dir * R, ny);
+
     // Loads of marching step k (row r) into register set J: the nine populations streaming
     // into row r, f_i(x, t) = f*_i(x - xi_i, t - 1). Steps past the last row load nothing.
+    // Called for k = 0, 1, 2, ... in order.
     auto issue = [&](int k, auto J) {
       constexpr int j = decltype(J)::value;
-      const int r = rstart + dir * k;
+      const int rw = rw_load;
+      rw_load = advance(rw);
+      const int rwm = rw == 0 ? ny - 1 : rw - 1;  // rows r - 1 and r + 1, wrapped
+      const int rwp = rw == ny - 1 ? 0 : rw + 1;
       const uint32_t rowoff = k < total ? 0u : OFF;
-      const long long rowo[3] = {(long long)wrapi(r - 1, ny) * nx, (long long)wrapi(r, ny) * nx,
-                                 (long long)wrapi(r + 1, ny) * nx};
+      if constexpr (WHOLE) {
+        const uint32_t rb[3] = {(uint32_t)rwm * rowb, (uint32_t)rw * rowb, (uint32_t)rwp * rowb};
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const Rsrc rs = mkrsrc(fb + (long long)i * cells + rowo[1 - V::cy(i)] - 1, rowbytes);
-        ld_row<S, M, CPL, WRAP>(rs, xb, wo, -V::cx(i), rowoff, fr[j % NSLOT][i]);
-        ld_row<S, M, CPL, WRAP>(rs, xbh, who, -V::cx(i), rowoff, hr[j % (PF + 1)][i]);
+        for (int i = 0; i < Q; ++i) {
+          const uint32_t so = (uint32_t)i * planeb + rb[1 - V::cy(i)];
+          ld_row<S, M, CPL, WRAP>(rin, xb, wo, -V::cx(i), rowoff, fr[j % NSLOT][i], so);
+          ld_row<S, M, CPL, WRAP>(rin, xbh, who, -V::cx(i), rowoff, hr[j % (PF + 1)][i], so);
+        }
+      } else {
+        const long long rowo[3] = {(long long)rwm * nx, (long long)rw * nx, (long long)rwp * nx};
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const Rsrc rs = mkrsrc(fb + (long long)i * cells + rowo[1 - V::cy(i)] - 1, rowbytes);
+          ld_row<S, M, CPL, WRAP>(rs, xb, wo, -V::cx(i), rowoff, fr[j % NSLOT][i], 0u);
+          ld_row<S, M, CPL, WRAP>(rs, xbh, who, -V::cx(i), rowoff, hr[j % (PF + 1)][i], 0u);
+        }
       }
     };
 
-    issue(0, std::integral_constant<int, 0>{});
-    if constexpr (PF > 1) issue(1, std::integral_constant<int, 1>{});
+    static_for<PF>([&](auto J) { issue(decltype(J)::value, J); });
     for (int k0 = 0; k0 < steps; k0 += NSLOT) {
       static_for<NSLOT>([&](auto J) {
         constexpr int j = decltype(J)::value;
@@ -208,7 +242,7 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
         // ---------------- 1. start the next row's loads, then psi of row r into the ring
         issue(k + PF, std::integral_constant<int, j + PF>{});
         const int r = rstart + dir * k;
-        M* ringrow = psis + ((r - rbase) % RING) * WIDTH;
+        M* ringrow = psis + ((r - rbase) & (RING - 1)) * WIDTH;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
           M sum = M(0);
@@ -235,8 +269,10 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
         const bool rowok = k >= 2 * R && k < total;
         const M* so[2 * R + 1];                      // ring rows of crow + dy, dy = o - R
 #pragma unroll
-        for (int o = 0; o <= 2 * R; ++o) so[o] = psis + ((crow - R + o - rbase) % RING) * WIDTH;
-        const long long orow = (long long)wrapi(crow, ny) * nx;
+        for (int o = 0; o <= 2 * R; ++o) so[o] = psis + ((crow - R + o - rbase) & (RING - 1)) * WIDTH;
+        const int cw = rw_coll;  // crow, wrapped
+        rw_coll = advance(cw);
+        const long long orow = (long long)cw * nx;
         M out[Q][CPL];
         M recv[5][CPL];
 #pragma unroll
@@ -281,9 +317,15 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
           }
         }
         const uint32_t so_ = rowok ? xbo : OFF;
+        if constexpr (WHOLE) {
+          const uint32_t orb = (uint32_t)cw * rowb;
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-          stb<S, M, CPL, SCL_STORE_AUX>(mkrsrc(ob + (long long)i * cells + orow, (uint32_t)nx * sizeof(S)), so_, out[i]);
+          for (int i = 0; i < Q; ++i) stb<S, M, CPL, SCL_STORE_AUX>(rout, so_, out[i], (uint32_t)i * planeb + orb);
+        } else {
+#pragma unroll
+          for (int i = 0; i < Q; ++i)
+            stb<S, M, CPL, SCL_STORE_AUX>(mkrsrc(ob + (long long)i * cells + orow, rowb), so_, out[i]);
+        }
         if (REC) {
           const long long g = dm.off + orow;
           const uint32_t sm = rowok ? xbm : OFF;
@@ -297,8 +339,13 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
       });
     }
   };
-  if (seam) march(std::true_type{});
-  else march(std::false_type{});
+  if (whole) {
+    if (seam) march(std::true_type{}, std::true_type{});
+    else march(std::false_type{}, std::true_type{});
+  } else {
+    if (seam) march(std::true_type{}, std::false_type{});
+    else march(std::false_type{}, std::false_type{});
+  }
 }
 
 }  // namespace scl
