@@ -212,6 +212,55 @@ def load_traffic(bytes_alg):
     return t.get("bytes_per_launch")
 
 
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)):
+        with open(f, newline="") as fh:
+            rows += list(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return rows
+
+
+def _counter_median(d, name_has, counter):
+    vals = [float(r["Counter_Value"]) for r in _csv_rows(d, "counter_collection.csv")
+            if name_has in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    if not vals:
+        raise SystemExit(f"no {counter} rows for a kernel named *{name_has}* under {d}")
+    return float(np.median(vals)), len(vals)
+
+
+def write_traffic(kt_dir, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
+    """Traffic of the step kernel per launch from rocprofv3 output directories: the kernel
+    trace's average duration, FETCH_SIZE and WRITE_SIZE (KiB per dispatch, median) of the step
+    kernel, each scaled by what the same counter reads for the device copy of known size
+    (bench.py --mode copy). Writes the file that the bench line's roofline.traffic reads."""
+    key = "k_step2d<float, float, 1, 512, 1, true, false>"
+    stats = [r for r in _csv_rows(kt_dir, "kernel_stats.csv") if key in r["Name"]]
+    if len(stats) != 1:
+        raise SystemExit(f"expected one kernel-stats row for {key}, found {len(stats)}")
+    avg_ns, calls = float(stats[0]["AverageNs"]), int(stats[0]["Calls"])
+    fk, _ = _counter_median(fetch_dir, key, "FETCH_SIZE")
+    wk, _ = _counter_median(write_dir, key, "WRITE_SIZE")
+    cf, _ = _counter_median(copy_fetch_dir, "copyBuffer", "FETCH_SIZE")
+    cw, _ = _counter_median(copy_write_dir, "copyBuffer", "WRITE_SIZE")
+    copy_bytes = 4 * (1 << 28)
+    fscale, wscale = copy_bytes / (cf * 1024), copy_bytes / (cw * 1024)
+    fb, wb = fk * 1024 * fscale, wk * 1024 * wscale
+    alg = 2 * 9 * 4 * DIMS[0] * DIMS[1]
+    t = {"kernel": "void scl::" + key, "kernel_hash": kernel_hash(), "avg_duration_ns": avg_ns, "calls": calls,
+         "fetch_kib_raw_median": fk, "write_kib_raw_median": wk, "copy_fetch_kib_raw": cf, "copy_write_kib_raw": cw,
+         "fetch_scale": fscale, "write_scale": wscale, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+         "bytes_per_launch": fb + wb, "bytes_alg_per_launch": alg, "traffic_over_alg": (fb + wb) / alg,
+         "fetch_over_alg_reads": fb / (alg / 2), "achieved_alg_GBs_from_trace": alg / avg_ns,
+         "achieved_traffic_GBs_from_trace": (fb + wb) / avg_ns}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(t, fh, indent=1)
+    print(json.dumps(t), flush=True)
+
+
 def copy_calibration():
     """A plain device copy of known size (for scaling the FETCH_SIZE / WRITE_SIZE counters)."""
     import torch
@@ -236,7 +285,13 @@ def main():
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--mode", default="bench", choices=["bench", "copy", "d3q19"],
                     help="copy: device copy for counter calibration; d3q19: the 3D leg alone")
+    ap.add_argument("--write-traffic", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="rocprofv3 output directories (kernel trace, FETCH_SIZE and WRITE_SIZE of the bench, "
+                         "the same counters of --mode copy): write the step kernel's measured traffic")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)

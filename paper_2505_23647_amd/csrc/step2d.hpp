@@ -188,7 +188,7 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
     // fr: populations of the rows between their load and their collision (R + 1 rows) plus
     // the row whose loads are in flight; hr: the same for the halo group (current + next).
     M fr[NSLOT][Q][CPL];
-    M hr[PF + 1][Q][CPL];
+    S hr[PF + 1][Q][CPL];  // kept in the storage type: only the halo lanes convert them
 #pragma unroll
     for (int a = 0; a < NSLOT; ++a)
 #pragma unroll
@@ -221,7 +221,7 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
         for (int i = 0; i < Q; ++i) {
           const uint32_t so = (uint32_t)i * planeb + rb[1 - V::cy(i)];
           ld_row<S, M, CPL, WRAP>(rin, xb, wo, -V::cx(i), rowoff, fr[j % NSLOT][i], so);
-          ld_row<S, M, CPL, WRAP>(rin, xbh, who, -V::cx(i), rowoff, hr[j % (PF + 1)][i], so);
+          ld_row<S, S, CPL, WRAP>(rin, xbh, who, -V::cx(i), rowoff, hr[j % (PF + 1)][i], so);
         }
       } else {
         const long long rowo[3] = {(long long)rwm * nx, (long long)rw * nx, (long long)rwp * nx};
@@ -229,7 +229,7 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
         for (int i = 0; i < Q; ++i) {
           const Rsrc rs = mkrsrc(fb + (long long)i * cells + rowo[1 - V::cy(i)] - 1, rowbytes);
           ld_row<S, M, CPL, WRAP>(rs, xb, wo, -V::cx(i), rowoff, fr[j % NSLOT][i], 0u);
-          ld_row<S, M, CPL, WRAP>(rs, xbh, who, -V::cx(i), rowoff, hr[j % (PF + 1)][i], 0u);
+          ld_row<S, S, CPL, WRAP>(rs, xbh, who, -V::cx(i), rowoff, hr[j % (PF + 1)][i], 0u);
         }
       }
     };
@@ -256,7 +256,7 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
           for (int c = 0; c < CPL; ++c) {
             M sum = M(0);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) sum += hr[j % (PF + 1)][i][c];
+            for (int i = 0; i < Q; ++i) sum += static_cast<M>(hr[j % (PF + 1)][i][c]);
             ringrow[qh + c] = psi_eval<M>(SHIFT ? rho0 + sum : sum, kind, eps, inv_eps);
           }
         }
