@@ -174,20 +174,50 @@ bool planes_fit_tiles(const scl_lattice_s* L) {
   return true;
 }
 
+// Sites of 2D marching strips w lanes wide (cpl sites per lane) that lie past a domain's width.
+long long strip_idle(const scl_lattice_s* L, int w, int cpl) {
+  long long idle = 0;
+  for (int k = 0; k < L->ndom; ++k) {
+    const long long ow = (long long)w * cpl;
+    idle += ((L->nx[k] + ow - 1) / ow * ow - L->nx[k]) * (long long)L->ny[k];
+  }
+  return idle;
+}
+
+// Automatic 2D strip: measured best on MI355X (4096^2, 24 vectors): 512 output lanes for 4-byte
+// storage, 256 for FP64; 256 for the reach-4 set (larger ring and register sets). Narrow
+// domains take narrower strips: the widest whose idle lanes (strip columns past a domain's
+// width) stay under half the sites.
+int auto_strip(const scl_lattice_s* L, int cpl) {
+  int w = (storage_bytes(L->prec) == 4 && L->set != 2 && cpl == 1) ? 512 : 256;
+  for (; w > 128; w /= 2)
+    if (strip_idle(L, w, cpl) * 2 <= L->cells) break;
+  return w;
+}
+
 scl_status build_items(scl_lattice_s* L) {
   std::vector<WorkItem> items;
-  // 2D tiles: as requested, or automatically for FP64 storage with the shell sets of reach 1
-  // and 2 when no other tiling is asked for (measured on MI355X, 4096^2, 24 vectors: 256-lane
-  // tiles of 64 x 24 sites take 0.468 ms per step against 0.512 ms for the best marching
-  // strips; for 4- and 2-byte storage the marching strips are as fast or faster)
+  // 2D tiles: as requested, or automatically (no tiling asked for, shell sets of reach 1 and 2)
+  //  * for FP64 storage: measured on MI355X, 4096^2, 24 vectors, 256-lane tiles of 64 x 24
+  //    sites take 0.468 ms per step against 0.512 ms for the best marching strips (for 4- and
+  //    2-byte storage the strips are as fast or faster there);
+  //  * for domains narrow enough that the automatic strips leave more than 1/8 of their lanes
+  //    idle: the 64 droplet and bubble domains of sides 64..544 run 48.5 GLUPS on 512-lane
+  //    tiles of 64 x 16 sites against 43.2 on 256-lane strips (30% idle lanes), FP32 shifted.
   L->tile2_eff = 0;
   if (L->d == 2 && !L->march_only) {
+    const bool asked = L->strip || L->seg || L->cpl_req;
     if (L->tile2) {
       L->tile2_eff = L->tile2;
       L->tile_ty_eff = L->tile_ty;
-    } else if (!L->strip && !L->seg && !L->cpl_req && L->prec == SCL_FP64 && L->set != 2 && planes_fit_tiles(L)) {
-      L->tile2_eff = 256;
-      L->tile_ty_eff = 24;
+    } else if (!asked && L->set != 2 && planes_fit_tiles(L)) {
+      if (L->prec == SCL_FP64) {
+        L->tile2_eff = 256;
+        L->tile_ty_eff = 24;
+      } else if (strip_idle(L, auto_strip(L, 1), 1) * 8 > L->cells) {
+        L->tile2_eff = 512;
+        L->tile_ty_eff = 16;
+      }
     }
   }
   if (L->tile2_eff) {
@@ -211,25 +241,9 @@ scl_status build_items(scl_lattice_s* L) {
     // cut occupancy to 3 waves per SIMD.
     L->cpl = L->cpl_req ? L->cpl_req : 1;
     if (L->cpl == 2 && !even) return fail(SCL_E_INVALID, "two sites per lane need even domain widths");
-    // output lanes per workgroup: measured best on MI355X (4096^2, 24 vectors): 512 for 4-byte
-    // storage, 256 for FP64; 256 for the reach-4 set (larger ring and register sets). Narrow
-    // domains take narrower strips: the widest whose idle lanes (strip columns past a domain's
-    // width) stay under half the sites. (64 domains 64..544 wide: 256-lane strips, 30% idle
-    // lanes, run 7% faster than 128-lane strips with 18%; 512 lanes, 46% idle, lose.)
-    if (L->strip) {
-      L->strip_eff = L->strip;
-    } else {
-      int w = (storage_bytes(L->prec) == 4 && L->set != 2 && L->cpl == 1) ? 512 : 256;
-      for (; w > 128; w /= 2) {
-        long long idle = 0;
-        for (int k = 0; k < L->ndom; ++k) {
-          const long long ow = (long long)w * L->cpl;
-          idle += ((L->nx[k] + ow - 1) / ow * ow - L->nx[k]) * (long long)L->ny[k];
-        }
-        if (idle * 2 <= L->cells) break;
-      }
-      L->strip_eff = w;
-    }
+    // output lanes per workgroup (64 domains 64..544 wide: 256-lane strips, 30% idle lanes,
+    // run 7% faster than 128-lane strips with 18%; 512 lanes, 46% idle, lose)
+    L->strip_eff = L->strip ? L->strip : auto_strip(L, L->cpl);
     const int outw = L->strip_eff * L->cpl;
     // rows per item: measured best on MI355X (4096^2, 24 vectors): 64 for FP16 storage, 32
     // otherwise. At 4096^2 with 512-lane strips, 32 rows make 1024 items, exactly two rounds of

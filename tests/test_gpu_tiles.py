@@ -109,7 +109,8 @@ def test_tiles_graph_replay():
 
 def test_tiles_selection_and_validation():
     """FP64 lattices with the reach-1 and reach-2 sets step through 256-lane 64 x 24 tiles unless
-    a tiling is requested; other precisions march; bad tile shapes are rejected."""
+    a tiling is requested, and so do narrow batched domains through 512-lane 64 x 16 tiles;
+    other lattices march; bad tile shapes are rejected."""
     say("case: tile selection and validation")
     G = coupling(0.2)
     lat = Lattice([(128, 96)], SCL_FP64).set_physics(1.0, G).set_stencil(*E8_2D)
@@ -122,6 +123,11 @@ def test_tiles_selection_and_validation():
     assert l4.get_tiling()[0] > 0
     l32 = Lattice([(128, 96)], SCL_FP32_SHIFTED).set_physics(1.0, G).set_stencil(*E8_2D)
     assert l32.get_tiling()[0] > 0
+    # narrow batched domains: 256-lane strips would leave 48% of their lanes idle
+    narrow = Lattice([(64, 64), (100, 100), (544, 544)], SCL_FP32_SHIFTED).set_physics(1.0, G).set_stencil(*E8_2D)
+    assert tuple(narrow.get_tiling()) == (-512, 16, 1)
+    wide = Lattice([(256, 256)] * 4, SCL_FP32_SHIFTED).set_physics(1.0, G).set_stencil(*E8_2D)
+    assert wide.get_tiling()[0] == 256
     for bad in ((-128, 16, 0), (-256, 12, 0), (-512, 8, 0), (-64, 0, 0)):
         with pytest.raises(SclError):
             lat.set_tiling(*bad)
