@@ -266,6 +266,42 @@ def test_full_size_c2_sampled_fp64_and_fp32():
         assert abs(m1[0] / m0[0] - 1) < (1e-13 if prec == SCL_FP64 else 1e-5)
 
 
+def test_full_size_c4_sampled_3d_fp32_and_fp64():
+    """512^3 D3Q19 with the 92-vector stencil (seeded weights near 3D E(8)), tau = 0.8,
+    n0 = 1 + U(-1e-2, 1e-2), in the bench's launch configuration (automatic tiling): after 2
+    steps, sampled sites (seam corners included) against oracle patches (exact light cone),
+    FP64 to 1e-12 and FP32 to 2e-6. The populations are read out into device memory and only
+    the samples are brought to the host."""
+    import torch
+    from paper_2505_23647_amd import stencil
+    say("case: full size 512^3 d3q19 sampled")
+    dims = (512, 512, 512)
+    u = synth.knob_draws(3, 3, 0.0, 1.0)
+    W = stencil.seeded_family3d(*u)[3]
+    codes = list(stencil.SHELLS_3D)
+    G = -1.2 * np.e ** 2
+    n0 = synth.around(dims, 1.0, 1e-2, seed=4)
+    rng = np.random.default_rng(11)
+    samples = [(0, 0, 0), (511, 511, 511), (0, 511, 255), (300, 2, 509)] + [tuple(v) for v in rng.integers(0, 512, (3, 3))]
+    steps = 2
+    refs = [patch_oracle(n0, dims, c, 3 * steps + 1, 0.8, G, codes, W, steps) for c in samples]
+    cells = 512 ** 3
+    for prec, tol in ((SCL_FP64, FP64_TOL), (SCL_FP32, 2e-6)):
+        lat = gpu_run([dims], prec, 0.8, G, codes, W, n0, steps)
+        out = torch.empty((19, cells), dtype=torch.float64, device="cuda")
+        B.check(B.lib().scl_get_populations(lat.h, out.data_ptr(), 1))
+        idx = torch.tensor([c[0] + 512 * (c[1] + 512 * c[2]) for c in samples], device="cuda")
+        f = out[:, idx].cpu().numpy()
+        del out
+        perm = perm_to_oracle(lat.xi, 3)
+        for k, (c, ref) in enumerate(zip(samples, refs)):
+            e = np.abs(f[perm, k] - ref).max() / np.abs(ref).max()
+            say(f"  precision {prec} site {c}: {e:.2e}")
+            assert e <= tol, (prec, c, e)
+        lat.close()
+        torch.cuda.empty_cache()
+
+
 def test_graph_replay_matches_plain_launches():
     say("case: hip graph replay")
     G = coupling(0.2)
