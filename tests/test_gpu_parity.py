@@ -302,6 +302,38 @@ def test_full_size_c4_sampled_3d_fp32_and_fp64():
         torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("prec,dims,tiling,tol", [(SCL_FP32, (8192, 8192), None, 2e-6),
+                                                 (SCL_FP64, (6144, 6144), (256, 32, 1), FP64_TOL),
+                                                 (SCL_FP64, (6144, 6144), (-256, 24, 0), FP64_TOL)])
+def test_states_over_2gib_sampled(prec, dims, tiling, tol):
+    """A domain whose state exceeds 2 GiB: the marching step addresses it through a descriptor
+    per row and plane instead of one for the whole state (the tiles need only each plane under
+    2 GiB). After 3 steps, sampled sites (seam corners included) against oracle patches."""
+    import torch
+    say(f"case: state over 2 GiB, precision {prec}, dims {dims}, tiling {tiling}")
+    G = coupling(0.2)
+    W = family2d_weights(0.6, 0.6 ** 2 * (16 / 105) / (4 / 7) ** 2)
+    n0 = synth.uniform(dims, 0.5, 1.5, seed=5)
+    rng = np.random.default_rng(8)
+    samples = [(0, 0), (dims[0] - 1, dims[1] - 1), (dims[0] - 1, 3), (5000, 6000)] + \
+        [tuple(v) for v in rng.integers(0, min(dims), (3, 2))]
+    steps = 3
+    refs = [patch_oracle(n0, dims, c, 3 * steps + 2, 1.0, G, E8_2D[0], W, steps) for c in samples]
+    lat = gpu_run([dims], prec, 1.0, G, E8_2D[0], W, n0, steps, tiling=tiling)
+    cells = dims[0] * dims[1]
+    out = torch.empty((9, cells), dtype=torch.float64, device="cuda")
+    B.check(B.lib().scl_get_populations(lat.h, out.data_ptr(), 1))
+    idx = torch.tensor([c[0] + dims[0] * c[1] for c in samples], device="cuda")
+    f = out[:, idx].cpu().numpy()
+    del out
+    perm = perm_to_oracle(lat.xi, 2)
+    for k, (c, ref) in enumerate(zip(samples, refs)):
+        e = np.abs(f[perm, k] - ref).max() / np.abs(ref).max()
+        assert e <= tol, (c, e)
+    lat.close()
+    torch.cuda.empty_cache()
+
+
 def test_graph_replay_matches_plain_launches():
     say("case: hip graph replay")
     G = coupling(0.2)
