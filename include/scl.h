@@ -212,7 +212,7 @@ scl_status scl_flat_observables(scl_lattice lat, const double* bulk, double* out
  *       64 x seg sites, no march. Needs every domain's population plane (sites x bytes per
  *       value) under 2 GiB (SCL_E_UNSUPPORTED otherwise). Results are bitwise those of the
  *       marching strips. With no tiling requested and the shell sets of reach 1 and 2, FP64
- *       storage runs 256-lane tiles of 64 x 24 sites, and domains so narrow that the automatic
+ *       storage runs 256-lane tiles of 64 x 16 sites, and domains so narrow that the automatic
  *       strips would leave more than 1/8 of their lanes idle run 512-lane tiles of 64 x 16
  *       sites; scl_adjoint's recording pass always marches.
  *   3D: strip = tile index (1: 64x4, 2: 64x8, 3: 32x8 output sites per workgroup;

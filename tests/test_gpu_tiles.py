@@ -108,13 +108,13 @@ def test_tiles_graph_replay():
 
 
 def test_tiles_selection_and_validation():
-    """FP64 lattices with the reach-1 and reach-2 sets step through 256-lane 64 x 24 tiles unless
+    """FP64 lattices with the reach-1 and reach-2 sets step through 256-lane 64 x 16 tiles unless
     a tiling is requested, and so do narrow batched domains through 512-lane 64 x 16 tiles;
     other lattices march; bad tile shapes are rejected."""
     say("case: tile selection and validation")
     G = coupling(0.2)
     lat = Lattice([(128, 96)], SCL_FP64).set_physics(1.0, G).set_stencil(*E8_2D)
-    assert tuple(lat.get_tiling()) == (-256, 24, 1)
+    assert tuple(lat.get_tiling()) == (-256, 16, 1)
     lat.set_tiling(128, 0, 0)
     assert lat.get_tiling()[0] == 128
     lat.set_tiling(-512, 24, 0)
