@@ -283,8 +283,9 @@ def main():
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
-    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "d3q19"],
-                    help="copy: device copy for counter calibration; d3q19: the 3D leg alone")
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "d3q19", "fp64", "fp16"],
+                    help="copy: device copy for counter calibration; d3q19: the 3D leg alone; "
+                         "fp64, fp16: the main workload in that storage precision alone")
     ap.add_argument("--write-traffic", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="rocprofv3 output directories (kernel trace, FETCH_SIZE and WRITE_SIZE of the bench, "
                          "the same counters of --mode copy): write the step kernel's measured traffic")
@@ -300,6 +301,18 @@ def main():
         return
     if args.mode == "d3q19":
         print(json.dumps({"d3q19_512cube_fp32": d3q19_leg(None, steps=args.steps)}), flush=True)
+        return
+    if args.mode in ("fp64", "fp16"):
+        from paper_2505_23647_amd import SCL_FP16S_FP32, SCL_FP64
+        prec, s = (SCL_FP64, 8) if args.mode == "fp64" else (SCL_FP16S_FP32, 2)
+        e4, e8, W, G, n0 = workload_inputs()
+        lv = make_lattice(prec, W, G, n0, None)
+        msv = timed(lv, args.steps, args.warmup)
+        cells = DIMS[0] * DIMS[1]
+        ach = 2 * 9 * s * cells / (msv / 1e3 / args.steps) / 1e9
+        print(json.dumps({args.mode: {"MLUPS": round(cells * args.steps / (msv / 1e3) / 1e6, 1),
+                                      "achieved_GBs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+                                      "tiling": list(lv.get_tiling())}}), flush=True)
         return
 
     import torch
