@@ -204,7 +204,8 @@ scl_status scl_flat_observables(scl_lattice lat, const double* bulk, double* out
 /* Tiling of the fused step.
  *   2D marching strips: strip = output lanes per workgroup (64, 128, 256 or 512; 0 =
  *       automatic: 512 for FP32 storage, 256 otherwise and for the reach-4 shell set); seg =
- *       rows one workgroup marches (>= 1; 0 = automatic: 64 for FP16 storage, 32 otherwise);
+ *       rows one workgroup marches (>= 1; 0 = automatic: 64 for 4- and 2-byte storage, 32
+ *       for FP64, halved down to 16 while the lattice gives fewer than 512 work items);
  *       cpl = sites per lane (1, or 2 for vector accesses, which needs every domain width even
  *       and a strip of at most 256; 0 = automatic: one site per lane).
  *   2D one-shot tiles: strip = -256 or -512 (lanes per workgroup), seg = rows per tile (8, 16,

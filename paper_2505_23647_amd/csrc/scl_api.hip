@@ -24,7 +24,7 @@ using namespace scl;
 
 // row ranges of one strip handed out together in the 2D item order
 #ifndef SCL_ITEM_BAND
-#define SCL_ITEM_BAND 8
+#define SCL_ITEM_BAND 4
 #endif
 
 namespace {
@@ -253,16 +253,29 @@ scl_status build_items(scl_lattice_s* L) {
     // run 7% faster than 128-lane strips with 18%; 512 lanes, 46% idle, lose)
     L->strip_eff = L->strip ? L->strip : auto_strip(L, L->cpl);
     const int outw = L->strip_eff * L->cpl;
-    // rows per item: measured best on MI355X (4096^2, 24 vectors): 64 for FP16 storage, 32
-    // otherwise. At 4096^2 with 512-lane strips, 32 rows make 1024 items, exactly two rounds of
-    // the 512 workgroups resident on the chip; 24, 28, 36 or 40 rows leave a partial round and
-    // lose 7-14%.
+    // rows per item: measured best on MI355X (4096^2, 24 vectors): 64 for 4- and 2-byte
+    // storage, 32 for FP64. At 4096^2 with 512-lane strips, 64 rows make 512 items, exactly one
+    // round of the 512 workgroups resident on the chip (0.236 ms per FP32 step, against 0.241
+    // for 32 rows, two rounds); 24, 28, 36 or 40 rows leave a partial round and lose 7-14%.
+    // Lattices too small to give 512 items at that height take lower ranges, down to 16 rows,
+    // so that every CU still gets work.
     int seg = L->seg;
-    if (seg <= 0) seg = L->prec == SCL_FP16S_FP32 ? 64 : 32;
+    if (seg <= 0) {
+      seg = storage_bytes(L->prec) == 8 ? 32 : 64;
+      auto nitems_at = [&](int sg) {
+        long long n = 0;
+        for (int k = 0; k < L->ndom; ++k)
+          n += (long long)((L->nx[k] + outw - 1) / outw) * ((L->ny[k] + sg - 1) / sg);
+        return n;
+      };
+      while (seg > 16 && nitems_at(seg) < 512) seg /= 2;
+    }
     // Order: bands of BAND row ranges; within a band, strip by strip, the ranges of the band
     // in order. The device hands each XCD a contiguous eighth of this list, so an XCD works on
     // a compact block of neighbouring strips and ranges whose shared halos meet in its L2.
-    // Consecutive ranges of a strip march in opposite directions.
+    // Consecutive ranges of a strip march in opposite directions. Bands of 4 ranges: at 4096^2
+    // with 512-lane strips and 64 rows, 0.236 ms per FP32 step against 0.246 for bands of 8 and
+    // 0.237 for whole strips (one strip per XCD).
     const int BAND = SCL_ITEM_BAND;
     for (int k = 0; k < L->ndom; ++k) {
       const int ns = (L->nx[k] + outw - 1) / outw;
@@ -1365,7 +1378,13 @@ scl_status scl_adjoint(scl_lattice L, const double* seed_n, const double* seed_f
     a.lam_bytes = lam_need;
   }
   constexpr int NO = 128;
-  std::vector<WorkItem> items = adjoint_items(L, NO, 32);
+  // rows per item: 32, halved down to 8 while the lattice gives fewer than 1024 items (one
+  // 128-lane workgroup per item holds few waves, so small batches need many items to fill
+  // the CUs: for 16 domains of 256^2 and 2000 steps the backward pass takes 0.152 s with 8
+  // rows against 0.184 s with 32)
+  int aseg = 32;
+  while (aseg > 8 && adjoint_items(L, NO, aseg).size() < 1024) aseg /= 2;
+  std::vector<WorkItem> items = adjoint_items(L, NO, aseg);
   WorkItem* d_items = nullptr;
   HIPCHK(hipMalloc(&d_items, sizeof(WorkItem) * items.size()));
   HIPCHK(hipMemcpy(d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice));
