@@ -216,9 +216,10 @@ scl_status scl_flat_observables(scl_lattice lat, const double* bulk, double* out
  *       storage runs 256-lane tiles of 64 x 16 sites, and domains so narrow that the automatic
  *       strips would leave more than 1/8 of their lanes idle run 512-lane tiles of 64 x 16
  *       sites; scl_adjoint's recording pass always marches.
- *   3D: strip = tile index (1: 64x4, 2: 64x8, 3: 32x8 output sites per workgroup;
- *       automatic until set: 64x4 for FP16 storage, 64x8 otherwise and for the reach-4
- *       set); seg = planes one workgroup marches; cpl is ignored.
+ *   3D: strip = tile index (1: 64x4, 2: 64x8, 3: 32x8, 4: 128x4 output sites per workgroup;
+ *       automatic until set: 128x4 for FP32 storage, 64x4 for FP16 storage, 64x8 for FP64
+ *       and for the reach-4 set, which runs tiles 2 and 3 only); seg = planes one workgroup
+ *       marches; cpl is ignored.
  * 0 keeps the current value (for cpl: automatic). */
 scl_status scl_set_tiling(scl_lattice lat, int32_t strip, int32_t seg, int32_t cpl);
 /* Current tiling (2D: the strip in use, or -lanes with seg = rows per tile when one-shot tiles

@@ -22,8 +22,8 @@ hipError_t launch_step3d(const StepArgs& a, const void* fin, void* fout) {
                        (const S*)fin, (S*)fout, (const M*)a.psi, a.doms, a.items, a.nitems);        \
     return hipGetLastError();                                                                     \
   }
-  SCL_3D_CASE(0, 1, 64, 4) SCL_3D_CASE(0, 2, 64, 8) SCL_3D_CASE(0, 3, 32, 8)
-  SCL_3D_CASE(1, 1, 64, 4) SCL_3D_CASE(1, 2, 64, 8) SCL_3D_CASE(1, 3, 32, 8)
+  SCL_3D_CASE(0, 1, 64, 4) SCL_3D_CASE(0, 2, 64, 8) SCL_3D_CASE(0, 3, 32, 8) SCL_3D_CASE(0, 4, 128, 4)
+  SCL_3D_CASE(1, 1, 64, 4) SCL_3D_CASE(1, 2, 64, 8) SCL_3D_CASE(1, 3, 32, 8) SCL_3D_CASE(1, 4, 128, 4)
   SCL_3D_CASE(2, 2, 64, 8) SCL_3D_CASE(2, 3, 32, 8)
 #undef SCL_3D_CASE
   return hipErrorInvalidValue;

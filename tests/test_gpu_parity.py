@@ -213,7 +213,7 @@ def test_d3q19_fp64_parity(codes, weights, dims, steps):
     G = coupling(0.2)
     W = family3d_weights(4 / 7, 16 / 105, 1 / 630) if weights == "family" else weights
     n0 = synth.around(dims, 1.0, 1e-2, seed=4)
-    for tile in (1, 2):
+    for tile in (1, 2, 4):
         lat = gpu_run([dims], SCL_FP64, 0.8, G, codes, W, n0, steps, tiling=(tile, 7))
         ora, _ = oracle_run(dims, 0.8, G, codes, W, n0, steps)
         assert compare_domain(lat, 0, ora, FP64_TOL) <= FP64_TOL, tile
@@ -226,7 +226,7 @@ def test_d3q19_fp32_error():
     dims = (40, 36, 34)
     n0 = synth.around(dims, 1.0, 1e-2, seed=4)
     ora, _ = oracle_run(dims, 0.8, G, [1, 2, 3, 4, 5, 6, 8], W, n0, 50)
-    for tile in (1, 2, 3):
+    for tile in (1, 2, 3, 4):
         lat = gpu_run([dims], SCL_FP32, 0.8, G, [1, 2, 3, 4, 5, 6, 8], W, n0, 50, tiling=(tile, 9))
         e = rel_err(lat.density(), ora.fields()["n"])
         say(f"  tile {tile}: {e:.2e}")
@@ -237,6 +237,24 @@ def test_d3q19_fp32_error():
         e = rel_err(lat.density(), ora.fields()["n"])
         say(f"  fp16 storage, tiling {tiling} (in use {lat.get_tiling()}): {e:.2e}")
         assert e < 2e-3
+
+
+def test_d3q19_tile_selection():
+    """Automatic 3D tiles: 128x4 for FP32 storage, 64x4 for FP16 storage, 64x8 for FP64 and for
+    the reach-4 set, which rejects the 64x4 and 128x4 tiles."""
+    from paper_2505_23647_amd import stencil
+    G = coupling(0.2)
+    W = family3d_weights(4 / 7, 16 / 105, 1 / 630)
+    shells = [1, 2, 3, 4, 5, 6, 8]
+    for prec, tile in ((SCL_FP32, 4), (SCL_FP32_SHIFTED, 4), (SCL_FP16S_FP32, 1), (SCL_FP64, 2)):
+        lat = Lattice([(32, 32, 32)], prec).set_physics(0.8, G).set_stencil(shells, W)
+        assert lat.get_tiling()[0] == tile, prec
+    r4 = list(stencil.TOLMAN_SHELLS_3D)
+    lat = Lattice([(32, 32, 32)], SCL_FP32).set_physics(0.8, G).set_stencil(r4, [0.01] * len(r4))
+    assert lat.get_tiling()[0] == 2
+    for bad in (1, 4, 5):
+        with pytest.raises(SclError):
+            lat.set_tiling(bad, 0, 0)
 
 
 def test_full_size_c2_sampled_fp64_and_fp32():
