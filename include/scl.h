@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define SCL_ABI_VERSION 2
+#define SCL_ABI_VERSION 3
 
 typedef struct scl_lattice_s* scl_lattice;
 
@@ -84,11 +84,24 @@ const char* scl_last_error(void);
  * (either may be NULL); returns Q, or -1 for an unknown vs. */
 int32_t scl_velocity_set(scl_velset vs, int32_t* xi, double* w);
 
+/* Device-memory source for lattices created afterwards (for callers that pool their device
+ * memory, e.g. a framework's caching allocator). Every device buffer a lattice holds, and the
+ * temporaries of its calls, come from alloc(bytes, ctx, stream) and go back through
+ * free_(ptr, ctx, stream), where stream is the lattice's hipStream_t: a release is stream
+ * ordered, and the memory may serve later work on that stream. alloc returns NULL when it
+ * cannot allocate (the call then fails with SCL_E_NOMEM or SCL_E_DEVICE). Both functions NULL
+ * (the default) means hipMalloc / hipFree. A lattice keeps the source it was created with until
+ * scl_destroy, whatever is installed later. Process-wide setting; not synchronised with
+ * concurrent scl_create calls on other threads. SCL_E_INVALID if exactly one function is NULL. */
+scl_status scl_set_allocator(void* (*alloc)(size_t bytes, void* ctx, void* stream),
+                             void (*free_)(void* ptr, void* ctx, void* stream), void* ctx);
+
 /* Create a lattice of ndom independent periodic domains.
  *   dims: ndom x 3 ints (nx, ny, nz), nz = 1 for D2Q9. Each extent must be >= 1; the
  *         domain must hold at least one site. Batched domains may differ in size.
  *   hip_stream: hipStream_t on which all work is ordered (NULL = default stream).
- * Allocates two population buffers (A/B) of Q x cells x sizeof(storage). */
+ * Allocates two population buffers (A/B) of Q x cells x sizeof(storage), from the source
+ * installed by scl_set_allocator (hipMalloc by default). */
 scl_status scl_create(scl_velset vs, scl_precision prec, int32_t ndom, const int32_t* dims,
                       void* hip_stream, scl_lattice* out);
 

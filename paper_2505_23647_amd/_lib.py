@@ -38,6 +38,7 @@ SIGNATURES = {
     "scl_abi_version": (_I32, []),
     "scl_last_error": (ctypes.c_char_p, []),
     "scl_velocity_set": (_I32, [_I32, _P, _P]),
+    "scl_set_allocator": (_I32, [_P, _P, _P]),
     "scl_create": (_I32, [_I32, _I32, _I32, _P, _P, ctypes.POINTER(_P)]),
     "scl_destroy": (_I32, [_P]),
     "scl_set_physics": (_I32, [_P, _P, _P, _I32, _P]),

@@ -45,12 +45,6 @@ struct AdjointState {
   int lam_cur = 0;             // buffer holding lambda after the last scl_adjoint
 };
 
-inline void adjoint_free(AdjointState& a) {
-  void* ps[] = {a.pool, a.rec, a.lam[0], a.lam[1], a.gpart};
-  for (void* p : ps)
-    if (p) (void)hipFree(p);
-  a = AdjointState();
-}
 
 // lambda_i(x) = seed(x) for every i (a loss that depends on the final state through n only)
 // or the given populations (natural layout, [Q][cells] per domain).

@@ -58,6 +58,15 @@ const int SET2N[NSETS2] = {2, 5, 8};
 const int SET3[NSETS3][SETW] = {{1, 2, 3}, {1, 2, 3, 4, 5, 6, 8}, {1, 2, 3, 4, 5, 6, 8, 9, 1009, 16, 18}};
 const int SET3N[NSETS3] = {3, 7, 11};
 
+// Device memory: from the hook installed by scl_set_allocator when there is one, else from
+// hipMalloc. A lattice keeps the hook that was installed when it was created.
+struct AllocHook {
+  void* (*alloc)(size_t, void*, void*) = nullptr;
+  void (*free_)(void*, void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+AllocHook g_hook;
+
 // 3D tile shapes selectable through scl_set_tiling(strip = index).
 struct Tile3 { int tx, ty; };
 const Tile3 TILES3[5] = {{0, 0}, {64, 4}, {64, 8}, {32, 8}, {128, 4}};
@@ -75,6 +84,7 @@ struct scl_lattice_s {
   hipStream_t stream = nullptr;    // caller's stream (may be the null stream)
   hipStream_t launch = nullptr;    // stream the step kernels go to (the capture stream while capturing)
   hipStream_t cap = nullptr;       // private stream used only to capture graphs
+  AllocHook hook;     // device memory source (scl_set_allocator at creation)
   void* A = nullptr;  // current state (post-collision values, pull layout)
   void* B = nullptr;  // scratch for the next state
   // physics
@@ -119,6 +129,32 @@ struct scl_lattice_s {
 };
 
 namespace {
+
+hipError_t dmalloc(const scl_lattice_s* L, void** p, size_t bytes) {
+  if (!L->hook.alloc) return hipMalloc(p, bytes);
+  *p = bytes ? L->hook.alloc(bytes, L->hook.ctx, (void*)L->stream) : nullptr;
+  return (*p || !bytes) ? hipSuccess : hipErrorOutOfMemory;
+}
+template <class T> hipError_t dmalloc(const scl_lattice_s* L, T** p, size_t bytes) {
+  void* v = nullptr;
+  const hipError_t e = dmalloc(L, &v, bytes);
+  *p = static_cast<T*>(v);
+  return e;
+}
+// Stream-ordered release: the memory may be handed out again for later work on the lattice's
+// stream (every kernel and copy of the library runs on that stream or is synchronised first).
+hipError_t dfree(const scl_lattice_s* L, void* p) {
+  if (!p) return hipSuccess;
+  if (!L->hook.alloc) return hipFree(p);
+  L->hook.free_(p, L->hook.ctx, (void*)L->stream);
+  return hipSuccess;
+}
+
+void adjoint_free(const scl_lattice_s* L, AdjointState& a) {
+  void* ps[] = {a.pool, a.rec, a.lam[0], a.lam[1], a.gpart};
+  for (void* p : ps) (void)dfree(L, p);
+  a = AdjointState();
+}
 
 std::vector<DomDev> host_doms(const scl_lattice_s* L) {
   std::vector<DomDev> v(L->ndom);
@@ -321,8 +357,8 @@ scl_status build_items(scl_lattice_s* L) {
           }
     }
   }
-  if (L->d_items) { HIPCHK(hipFree(L->d_items)); L->d_items = nullptr; }
-  HIPCHK(hipMalloc(&L->d_items, sizeof(WorkItem) * items.size()));
+  if (L->d_items) { HIPCHK(dfree(L, L->d_items)); L->d_items = nullptr; }
+  HIPCHK(dmalloc(L, &L->d_items, sizeof(WorkItem) * items.size()));
   HIPCHK(hipMemcpy(L->d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice));
   L->nitems = (int)items.size();
   L->dirty_items = false;
@@ -332,7 +368,7 @@ scl_status build_items(scl_lattice_s* L) {
 scl_status sync_params(scl_lattice_s* L) {
   if (L->dirty_doms) {
     std::vector<DomDev> v = host_doms(L);
-    if (!L->d_doms) HIPCHK(hipMalloc(&L->d_doms, sizeof(DomDev) * L->ndom));
+    if (!L->d_doms) HIPCHK(dmalloc(L, &L->d_doms, sizeof(DomDev) * L->ndom));
     HIPCHK(hipMemcpyAsync(L->d_doms, v.data(), sizeof(DomDev) * L->ndom, hipMemcpyHostToDevice, L->stream));
     L->h_doms = v;
     HIPCHK(hipStreamSynchronize(L->stream));
@@ -465,11 +501,11 @@ scl_status do_steps(scl_lattice_s* L, int64_t n) {
 scl_status ensure_scratch(scl_lattice_s* L) {
   if (!L->d_n) {
     const size_t c = (size_t)L->cells;
-    HIPCHK(hipMalloc(&L->d_n, c * sizeof(double)));
-    HIPCHK(hipMalloc(&L->d_psi, c * sizeof(double)));
-    HIPCHK(hipMalloc(&L->d_j, 3 * c * sizeof(double)));
-    HIPCHK(hipMalloc(&L->d_F, 3 * c * sizeof(double)));
-    HIPCHK(hipMalloc(&L->d_tmp, (L->d == 3 ? 6 : 3) * c * sizeof(double)));
+    HIPCHK(dmalloc(L, &L->d_n, c * sizeof(double)));
+    HIPCHK(dmalloc(L, &L->d_psi, c * sizeof(double)));
+    HIPCHK(dmalloc(L, &L->d_j, 3 * c * sizeof(double)));
+    HIPCHK(dmalloc(L, &L->d_F, 3 * c * sizeof(double)));
+    HIPCHK(dmalloc(L, &L->d_tmp, (L->d == 3 ? 6 : 3) * c * sizeof(double)));
   }
   return SCL_OK;
 }
@@ -647,6 +683,14 @@ int32_t scl_velocity_set(scl_velset vs, int32_t* xi, double* w) {
   return -1;
 }
 
+scl_status scl_set_allocator(void* (*alloc)(size_t, void*, void*), void (*free_)(void*, void*, void*), void* ctx) {
+  if ((alloc == nullptr) != (free_ == nullptr)) return fail(SCL_E_INVALID, "give both allocator functions, or neither");
+  g_hook.alloc = alloc;
+  g_hook.free_ = free_;
+  g_hook.ctx = alloc ? ctx : nullptr;
+  return SCL_OK;
+}
+
 scl_status scl_create(scl_velset vs, scl_precision prec, int32_t ndom, const int32_t* dims, void* hip_stream,
                       scl_lattice* out) {
   if (!out) return fail(SCL_E_INVALID, "out is NULL");
@@ -678,6 +722,7 @@ scl_status scl_create(scl_velset vs, scl_precision prec, int32_t ndom, const int
   L->cells = tot;
   L->stream = (hipStream_t)hip_stream;
   L->launch = L->stream;
+  L->hook = g_hook;
   L->tau.assign(ndom, 1.0);
   L->G.assign(ndom, 0.0);
   L->psi_param.assign(ndom, 0.0);
@@ -685,14 +730,14 @@ scl_status scl_create(scl_velset vs, scl_precision prec, int32_t ndom, const int
   L->aF.assign(ndom, 0.0);
   L->Wslot.assign((size_t)ndom * MAX_SHELLS, 0.0);
   const size_t bytes = (size_t)L->Q * tot * storage_bytes(prec);
-  if (hipMalloc(&L->A, bytes) != hipSuccess || hipMalloc(&L->B, bytes) != hipSuccess) {
-    if (L->A) (void)hipFree(L->A);
+  if (dmalloc(L.get(), &L->A, bytes) != hipSuccess || dmalloc(L.get(), &L->B, bytes) != hipSuccess) {
+    if (L->A) (void)dfree(L.get(), L->A);
     (void)hipGetLastError();
     return fail(SCL_E_NOMEM, "population buffers do not fit in device memory");
   }
-  if (L->d == 3 && hipMalloc(&L->d_psi3, (size_t)tot * (prec == SCL_FP64 ? 8 : 4)) != hipSuccess) {
-    (void)hipFree(L->A);
-    (void)hipFree(L->B);
+  if (L->d == 3 && dmalloc(L.get(), &L->d_psi3, (size_t)tot * (prec == SCL_FP64 ? 8 : 4)) != hipSuccess) {
+    (void)dfree(L.get(), L->A);
+    (void)dfree(L.get(), L->B);
     (void)hipGetLastError();
     return fail(SCL_E_NOMEM, "the psi array does not fit in device memory");
   }
@@ -705,11 +750,11 @@ scl_status scl_create(scl_velset vs, scl_precision prec, int32_t ndom, const int
 scl_status scl_destroy(scl_lattice L) {
   if (!L) return SCL_OK;
   drop_graph(L);
-  adjoint_free(L->adj);
+  adjoint_free(L, L->adj);
   void* ptrs[] = {L->A, L->B, L->d_doms, L->d_items, L->d_n, L->d_psi, L->d_j, L->d_F, L->d_tmp, L->d_part,
                   L->d_psi3};
   for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+    if (p) (void)dfree(L, p);
   if (L->cap) (void)hipStreamDestroy(L->cap);
   if (L->ev0) (void)hipEventDestroy(L->ev0);
   if (L->ev1) (void)hipEventDestroy(L->ev1);
@@ -818,7 +863,7 @@ scl_status scl_init_density(scl_lattice L, const double* n0, int32_t is_dev) {
   }
   L->dirty_doms = true;
   double* dn = nullptr;
-  HIPCHK(hipMalloc(&dn, h.size() * sizeof(double)));
+  HIPCHK(dmalloc(L, &dn, h.size() * sizeof(double)));
   HIPCHK(hipMemcpyAsync(dn, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, L->stream));
   std::vector<DomDev> doms = host_doms(L);
   for (int k = 0; k < L->ndom; ++k) {
@@ -834,7 +879,7 @@ scl_status scl_init_density(scl_lattice L, const double* n0, int32_t is_dev) {
     HIPCHK(hipGetLastError());
   }
   HIPCHK(hipStreamSynchronize(L->stream));
-  HIPCHK(hipFree(dn));
+  HIPCHK(dfree(L, dn));
   L->have_state = true;
   L->steps = 0;
   L->adj.valid = false;
@@ -902,7 +947,7 @@ scl_status scl_get_populations(scl_lattice L, double* out, int32_t is_dev) {
   if (s != SCL_OK) return s;
   const size_t n = (size_t)L->Q * L->cells;
   double* dst = out;
-  if (!is_dev) HIPCHK(hipMalloc(&dst, n * sizeof(double)));
+  if (!is_dev) HIPCHK(dmalloc(L, &dst, n * sizeof(double)));
   std::vector<DomDev> doms = host_doms(L);
   for (int k = 0; k < L->ndom; ++k) {
     const long long c = (long long)L->nx[k] * L->ny[k] * L->nz[k];
@@ -919,7 +964,7 @@ scl_status scl_get_populations(scl_lattice L, double* out, int32_t is_dev) {
   HIPCHK(hipStreamSynchronize(L->stream));
   if (!is_dev) {
     HIPCHK(hipMemcpy(out, dst, n * sizeof(double), hipMemcpyDeviceToHost));
-    HIPCHK(hipFree(dst));
+    HIPCHK(dfree(L, dst));
   }
   return SCL_OK;
 }
@@ -933,7 +978,7 @@ scl_status scl_set_populations(scl_lattice L, const double* in, int32_t is_dev) 
   const double* src = in;
   double* tmp = nullptr;
   if (!is_dev) {
-    HIPCHK(hipMalloc(&tmp, n * sizeof(double)));
+    HIPCHK(dmalloc(L, &tmp, n * sizeof(double)));
     HIPCHK(hipMemcpy(tmp, in, n * sizeof(double), hipMemcpyHostToDevice));
     src = tmp;
   }
@@ -951,7 +996,7 @@ scl_status scl_set_populations(scl_lattice L, const double* in, int32_t is_dev) 
     HIPCHK(hipGetLastError());
   }
   HIPCHK(hipStreamSynchronize(L->stream));
-  if (tmp) HIPCHK(hipFree(tmp));
+  if (tmp) HIPCHK(dfree(L, tmp));
   L->adj.valid = false;
   drop_graph(L);
   return SCL_OK;
@@ -963,15 +1008,15 @@ scl_status scl_reduce_conserved(scl_lattice L, double* mass, double* momentum) {
   if (s != SCL_OK) return s;
   const int nv = 1 + L->d;
   double* d_out = nullptr;
-  HIPCHK(hipMalloc(&d_out, sizeof(double) * nv * L->ndom));
+  HIPCHK(dmalloc(L, &d_out, sizeof(double) * nv * L->ndom));
   for (int k = 0; k < L->ndom; ++k) {
     const long long c = (long long)L->nx[k] * L->ny[k] * L->nz[k];
     const long long chunk = 4096;
     const int nb = (int)((c + chunk - 1) / chunk);
     if ((size_t)nb * nv > L->part_cap) {
-      if (L->d_part) HIPCHK(hipFree(L->d_part));
+      if (L->d_part) HIPCHK(dfree(L, L->d_part));
       L->part_cap = (size_t)nb * nv;
-      HIPCHK(hipMalloc(&L->d_part, sizeof(double) * L->part_cap));
+      HIPCHK(dmalloc(L, &L->d_part, sizeof(double) * L->part_cap));
     }
     if (L->d == 2)
       hipLaunchKernelGGL(k_reduce_partial<2>, dim3(nb), dim3(RED_NT), 0, L->stream, L->d_n, L->d_j, L->d_F, L->d_part, L->cells, L->off[k], c, chunk);
@@ -983,7 +1028,7 @@ scl_status scl_reduce_conserved(scl_lattice L, double* mass, double* momentum) {
   std::vector<double> h((size_t)nv * L->ndom);
   HIPCHK(hipMemcpyAsync(h.data(), d_out, h.size() * sizeof(double), hipMemcpyDeviceToHost, L->stream));
   HIPCHK(hipStreamSynchronize(L->stream));
-  HIPCHK(hipFree(d_out));
+  HIPCHK(dfree(L, d_out));
   bool finite = true;
   for (int k = 0; k < L->ndom; ++k) {
     mass[k] = h[(size_t)k * nv];
@@ -1003,8 +1048,12 @@ scl_status scl_get_pressure_tensor(scl_lattice L, double* out, int32_t is_dev) {
   if (L->d == 3) {
     const std::vector<PTermDev> terms = ptensor_link_terms(L);
     PTermDev* d_terms = nullptr;
-    HIPCHK(hipMalloc(&d_terms, terms.size() * sizeof(PTermDev)));
-    std::unique_ptr<PTermDev, hipError_t (*)(void*)> guard(d_terms, hipFree);
+    HIPCHK(dmalloc(L, &d_terms, terms.size() * sizeof(PTermDev)));
+    struct Guard {
+      const scl_lattice_s* L;
+      void* p;
+      ~Guard() { (void)dfree(L, p); }
+    } guard{L, d_terms};
     HIPCHK(hipMemcpyAsync(d_terms, terms.data(), terms.size() * sizeof(PTermDev), hipMemcpyHostToDevice, L->stream));
     for (int k = 0; k < L->ndom; ++k) {
       const long long c = (long long)L->nx[k] * L->ny[k] * L->nz[k];
@@ -1311,10 +1360,10 @@ scl_status scl_checkpointed_forward(scl_lattice L, int64_t nsteps, int32_t every
   const int nfull = (int)(nsteps / every);
   const int slots = nfull + 2;  // states at 0, every, ..., nfull*every, and the final one
   if (a.pool_bytes < (size_t)slots * sb) {
-    if (a.pool) HIPCHK(hipFree(a.pool));
+    if (a.pool) HIPCHK(dfree(L, a.pool));
     a.pool = nullptr;
     a.pool_bytes = 0;
-    if (hipMalloc(&a.pool, (size_t)slots * sb) != hipSuccess) {
+    if (dmalloc(L, &a.pool, (size_t)slots * sb) != hipSuccess) {
       (void)hipGetLastError();
       return fail(SCL_E_NOMEM, "checkpoint pool does not fit in device memory");
     }
@@ -1366,17 +1415,17 @@ scl_status scl_adjoint(scl_lattice L, const double* seed_n, const double* seed_f
   // buffers
   const size_t rec_need = (size_t)every * 5 * C * ms;
   if (a.rec_bytes < rec_need) {
-    if (a.rec) HIPCHK(hipFree(a.rec));
+    if (a.rec) HIPCHK(dfree(L, a.rec));
     a.rec = nullptr;
-    if (hipMalloc(&a.rec, rec_need) != hipSuccess) { (void)hipGetLastError(); a.rec_bytes = 0; return fail(SCL_E_NOMEM, "recompute buffer does not fit"); }
+    if (dmalloc(L, &a.rec, rec_need) != hipSuccess) { (void)hipGetLastError(); a.rec_bytes = 0; return fail(SCL_E_NOMEM, "recompute buffer does not fit"); }
     a.rec_bytes = rec_need;
   }
   const size_t lam_need = (size_t)L->Q * C * ms;
   if (a.lam_bytes < lam_need) {
     for (int b = 0; b < 2; ++b) {
-      if (a.lam[b]) HIPCHK(hipFree(a.lam[b]));
+      if (a.lam[b]) HIPCHK(dfree(L, a.lam[b]));
       a.lam[b] = nullptr;
-      if (hipMalloc(&a.lam[b], lam_need) != hipSuccess) { (void)hipGetLastError(); a.lam_bytes = 0; return fail(SCL_E_NOMEM, "adjoint buffers do not fit"); }
+      if (dmalloc(L, &a.lam[b], lam_need) != hipSuccess) { (void)hipGetLastError(); a.lam_bytes = 0; return fail(SCL_E_NOMEM, "adjoint buffers do not fit"); }
     }
     a.lam_bytes = lam_need;
   }
@@ -1389,13 +1438,13 @@ scl_status scl_adjoint(scl_lattice L, const double* seed_n, const double* seed_f
   while (aseg > 8 && adjoint_items(L, NO, aseg).size() < 1024) aseg /= 2;
   std::vector<WorkItem> items = adjoint_items(L, NO, aseg);
   WorkItem* d_items = nullptr;
-  HIPCHK(hipMalloc(&d_items, sizeof(WorkItem) * items.size()));
+  HIPCHK(dmalloc(L, &d_items, sizeof(WorkItem) * items.size()));
   HIPCHK(hipMemcpy(d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice));
   const int nitems = (int)items.size();
   const int NSG = 1 + ADJ_MAXS;
   if (a.gpart_cap < (size_t)nitems * NSG) {
-    if (a.gpart) HIPCHK(hipFree(a.gpart));
-    HIPCHK(hipMalloc(&a.gpart, sizeof(double) * nitems * NSG));
+    if (a.gpart) HIPCHK(dfree(L, a.gpart));
+    HIPCHK(dmalloc(L, &a.gpart, sizeof(double) * nitems * NSG));
     a.gpart_cap = (size_t)nitems * NSG;
   }
   // seed
@@ -1426,7 +1475,7 @@ scl_status scl_adjoint(scl_lattice L, const double* seed_n, const double* seed_f
         MacroRec<float> r{(float*)base, (float*)base + C, (float*)base + 3 * C, C};
         e = launch_step(L, L->A, L->B, nullptr, &r);
       }
-      if (e != hipSuccess) { (void)hipFree(d_items); return fail(SCL_E_DEVICE, std::string("recompute: ") + hipGetErrorString(e)); }
+      if (e != hipSuccess) { (void)dfree(L, d_items); return fail(SCL_E_DEVICE, std::string("recompute: ") + hipGetErrorString(e)); }
       std::swap(L->A, L->B);
     }
     // adjoint steps, last to first
@@ -1450,7 +1499,7 @@ scl_status scl_adjoint(scl_lattice L, const double* seed_n, const double* seed_f
   std::vector<double> part((size_t)nitems * NSG);
   HIPCHK(hipMemcpyAsync(part.data(), a.gpart, part.size() * sizeof(double), hipMemcpyDeviceToHost, L->stream));
   HIPCHK(hipStreamSynchronize(L->stream));
-  HIPCHK(hipFree(d_items));
+  HIPCHK(dfree(L, d_items));
   a.lam_cur = cur;
   // per-domain sums in item order; slot order -> the caller's shells
   const int NS = SET2N[L->set];
@@ -1472,14 +1521,14 @@ scl_status scl_get_adjoint_populations(scl_lattice L, double* out, int32_t is_de
   if (!a.lam[a.lam_cur]) return fail(SCL_E_STATE, "no adjoint has been computed");
   const size_t n = (size_t)L->Q * L->cells;
   double* dst = out;
-  if (!is_dev) HIPCHK(hipMalloc(&dst, n * sizeof(double)));
+  if (!is_dev) HIPCHK(dmalloc(L, &dst, n * sizeof(double)));
   if (L->prec == SCL_FP64) hipLaunchKernelGGL(k_adj_get<double>, dim3(blocks_for((long long)n, 256)), dim3(256), 0, L->stream, (const double*)a.lam[a.lam_cur], dst, (long long)n);
   else hipLaunchKernelGGL(k_adj_get<float>, dim3(blocks_for((long long)n, 256)), dim3(256), 0, L->stream, (const float*)a.lam[a.lam_cur], dst, (long long)n);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(L->stream));
   if (!is_dev) {
     HIPCHK(hipMemcpy(out, dst, n * sizeof(double), hipMemcpyDeviceToHost));
-    HIPCHK(hipFree(dst));
+    HIPCHK(dfree(L, dst));
   }
   return SCL_OK;
 }

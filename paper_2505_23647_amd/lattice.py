@@ -21,6 +21,39 @@ def _is_torch_cuda(a):
     return hasattr(a, "is_cuda") and a.is_cuda
 
 
+_ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+# Every callback pair ever installed stays referenced: lattices created with it free through
+# it until they are destroyed, even after another source has been installed.
+_installed_hooks = []
+
+
+def set_allocator(alloc=None, free=None):
+    """Device-memory source of the lattices created afterwards (scl_set_allocator).
+
+    alloc(nbytes, stream) -> device pointer as an int (0 if it cannot allocate);
+    free(ptr, stream). stream is the lattice's hipStream_t as an int (0: the null stream).
+    Both None restores hipMalloc / hipFree.
+    """
+    if alloc is None and free is None:
+        check(lib().scl_set_allocator(None, None, None))
+        return
+    if alloc is None or free is None:
+        raise ValueError("give both functions, or neither")
+    a = _ALLOC_T(lambda n, ctx, stream: alloc(int(n), stream or 0) or None)
+    f = _FREE_T(lambda p, ctx, stream: free(int(p), stream or 0))
+    _installed_hooks.append((a, f))
+    check(lib().scl_set_allocator(ctypes.cast(a, ctypes.c_void_p), ctypes.cast(f, ctypes.c_void_p), None))
+
+
+def use_torch_allocator():
+    """Lattices created afterwards take their device memory from torch's caching allocator."""
+    import torch
+
+    set_allocator(lambda n, stream: torch.cuda.caching_allocator_alloc(n, stream=stream),
+                  lambda p, stream: torch.cuda.caching_allocator_delete(p))
+
+
 def velocity_set(vs: int):
     xi = np.zeros((19, 3), dtype=np.int32)
     w = np.zeros(19)

@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported_and_bound():
 
 
 def test_abi_version():
-    assert B.lib().scl_abi_version() == 2
+    assert B.lib().scl_abi_version() == 3
 
 
 def test_velocity_sets_match_oracle_sets():
@@ -59,3 +59,11 @@ def test_create_rejects_bad_arguments_before_device_work():
     assert b"extent" in L.scl_last_error()
     assert L.scl_create(B.SCL_D2Q9, B.SCL_FP64, 1, p, None, None) == B.SCL_E_INVALID
     assert L.scl_destroy(None) == B.SCL_OK
+
+
+def test_allocator_hook_arguments():
+    """scl_set_allocator takes both functions or neither (no device work involved)."""
+    from paper_2505_23647_amd import lattice
+    a = lattice._ALLOC_T(lambda n, ctx, stream: None)
+    assert B.lib().scl_set_allocator(ctypes.cast(a, ctypes.c_void_p), None, None) == B.SCL_E_INVALID
+    assert B.lib().scl_set_allocator(None, None, None) == B.SCL_OK
