@@ -165,8 +165,11 @@ __host__ __device__ inline int wrapi(int a, int n) {
 // ------------------------------------------------------------------ pseudopotential
 template <class M> __device__ inline M psi_eval(M n, int kind, M eps, M inv_eps);
 
+// float, psi = exp(-1/n): exp2 of -log2(e)/n through the hardware reciprocal and the hardware
+// base-2 exponential (three instructions; within 3 ulp for the densities of a Shan-Chen fluid,
+// where -log2(e)/n stays far from the exponential's denormal range).
 template <> __device__ inline float psi_eval<float>(float n, int kind, float eps, float inv_eps) {
-  if (kind == 0) return expf(-__builtin_amdgcn_rcpf(n));
+  if (kind == 0) return __builtin_amdgcn_exp2f(-1.44269504088896341f * __builtin_amdgcn_rcpf(n));
   if (kind == 1) return powf(n / (eps + n), inv_eps);
   return 1.0f - expf(-n);
 }

@@ -188,6 +188,7 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
     // fr: populations of the rows between their load and their collision (R + 1 rows) plus
     // the row whose loads are in flight; hr: the same for the halo group (current + next).
     M fr[NSLOT][Q][CPL];
+    M nsum[NSLOT][CPL];  // sum of each row's stored values, formed for psi, reused by the collision
     S hr[PF + 1][Q][CPL];  // kept in the storage type: only the halo lanes convert them
 #pragma unroll
     for (int a = 0; a < NSLOT; ++a)
@@ -195,6 +196,10 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
       for (int i = 0; i < Q; ++i)
 #pragma unroll
         for (int c = 0; c < CPL; ++c) fr[a][i][c] = M(0);
+#pragma unroll
+    for (int a = 0; a < NSLOT; ++a)
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) nsum[a][c] = M(0);
 
     // Wrapped row of the next load and of the next collision, advanced by one row per marching
     // step (no division in the loop).
@@ -248,6 +253,7 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
           M sum = M(0);
 #pragma unroll
           for (int i = 0; i < Q; ++i) sum += fr[j][i][c];
+          nsum[j][c] = sum;
           const M p = psi_eval<M>(SHIFT ? rho0 + sum : sum, kind, eps, inv_eps);
           if (need) ringrow[q + c] = p;
         }
@@ -296,11 +302,11 @@ k_step2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
           const M Fx = gpre * psic * ax;
           const M Fy = gpre * psic * ay;
           M f[Q];
-          M sum = M(0), jx = M(0), jy = M(0);
+          const M sum = nsum[js][c];
+          M jx = M(0), jy = M(0);
 #pragma unroll
           for (int i = 0; i < Q; ++i) {
             f[i] = fr[js][i][c];
-            sum += f[i];
             if (V::cx(i) != 0) jx += M(V::cx(i)) * f[i];
             if (V::cy(i) != 0) jy += M(V::cy(i)) * f[i];
           }

@@ -73,12 +73,14 @@ k_tile2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
       ldb<S, M, 1>(r, on ? vo[1 - V::cx(i)] : OFF, f + i);
     }
   };
-  auto density = [&](const M* f) {
+  // sum of a site's stored values (the density, less rho0 for shifted storage)
+  auto vsum = [&](const M* f) {
     M s = M(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) s += f[i];
-    return SHIFT ? rho0 + s : s;
+    return s;
   };
+  auto psi_of = [&](M s) { return psi_eval<M>(SHIFT ? rho0 + s : s, kind, eps, inv_eps); };
 
   // ---- 1. pulls: the lane's tile sites, its rim-row sites, its side sites
   M fi[KI][Q];
@@ -129,22 +131,24 @@ k_tile2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
   }
 
   // ---- 2. psi of every pulled site into LDS
+  M ssum[KI];  // the tile sites' sums, reused by the collision
 #pragma unroll
   for (int k = 0; k < KI; ++k) {
     const int ly = w + NW * k + R;
-    const M p = psi_eval<M>(density(fi[k]), kind, eps, inv_eps);
+    ssum[k] = vsum(fi[k]);
+    const M p = psi_of(ssum[k]);
     if (xin && y0 + w + NW * k < ye) psis[ly * LW + lane + R] = p;
   }
 #pragma unroll
   for (int k = 0; k < KH; ++k) {
     const int h = w + NW * k;
     const int ly = h < R ? h : (ye - y0) + R + (h - R);
-    const M p = psi_eval<M>(density(fh[k]), kind, eps, inv_eps);
+    const M p = psi_of(vsum(fh[k]));
     if (xin && h < 2 * R) psis[ly * LW + lane + R] = p;
   }
 #pragma unroll
   for (int k = 0; k < KS; ++k) {
-    const M p = psi_eval<M>(density(fs[k]), kind, eps, inv_eps);
+    const M p = psi_of(vsum(fs[k]));
     if (lds_side[k] >= 0) psis[lds_side[k]] = p;
   }
   __syncthreads();
@@ -171,10 +175,10 @@ k_tile2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
     for (int s = 0; s < SH::NS; ++s) { ax += M(dm.W[s]) * dxs[s]; ay += M(dm.W[s]) * dys[s]; }
     const M Fx = gpre * psic * ax;
     const M Fy = gpre * psic * ay;
-    M sum = M(0), jx = M(0), jy = M(0);
+    const M sum = ssum[k];
+    M jx = M(0), jy = M(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      sum += fi[k][i];
       if (V::cx(i) != 0) jx += M(V::cx(i)) * fi[k][i];
       if (V::cy(i) != 0) jy += M(V::cy(i)) * fi[k][i];
     }
