@@ -248,7 +248,7 @@ __device__ __forceinline__ void collide_emit(const M* f, M base, M nn, M ux, M u
       if constexpr (cy != 0) { xu += M(cy) * uy; xF += M(cy) * Fy; }
       if constexpr (cz != 0) { xu += M(cz) * uz; xF += M(cz) * Fz; }
       const M E = M(4.5) * xu * xu - uu15;
-      const M Se = M(9) * xu * xF - aff45 * xF * xF - uF3;
+      const M Se = xF * (M(9) * xu - aff45 * xF) - uF3;
       const M A = w * (obase + on * E) + (kappa * w) * Se;
       const M B = (M(3) * w) * (on * xu + kappa * xF);
       emit(i, om1 * f[i] + (A + B));
