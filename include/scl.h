@@ -222,21 +222,23 @@ scl_status scl_flat_observables(scl_lattice lat, const double* bulk, double* out
  *       cpl = sites per lane (1, or 2 for vector accesses, which needs every domain width even
  *       and a strip of at most 256; 0 = automatic: one site per lane).
  *   2D one-shot tiles: strip = -256 or -512 (lanes per workgroup), seg = rows per tile (8, 16,
- *       24 or 32; 0 = 16; 512 lanes need at least 16), cpl ignored: one workgroup per tile of
- *       64 x seg sites, no march. Needs every domain's population plane (sites x bytes per
+ *       24 or 32; 0 = 16; 512 lanes need at least 16), cpl = tile width in 64-column units (0 or
+ *       1: 64, 2: 128): one workgroup per tile of 64 x seg or 128 x seg sites, no march. Needs every domain's population plane (sites x bytes per
  *       value) under 2 GiB (SCL_E_UNSUPPORTED otherwise). Results are bitwise those of the
  *       marching strips. With no tiling requested and the shell sets of reach 1 and 2, FP64
- *       storage runs 256-lane tiles of 64 x 16 sites, and domains so narrow that the automatic
+ *       storage runs 256-lane tiles of 128 x 8 sites; domains so narrow that the automatic
  *       strips would leave more than 1/8 of their lanes idle run 512-lane tiles of 64 x 16
- *       sites; scl_adjoint's recording pass always marches.
+ *       sites; FP16 storage otherwise runs 256-lane tiles of 128 x 16 sites; scl_adjoint's
+ *       recording pass always marches.
  *   3D: strip = tile index (1: 64x4, 2: 64x8, 3: 32x8, 4: 128x4 output sites per workgroup;
  *       automatic until set: 128x4 for FP32 storage, 64x4 for FP16 storage, 64x8 for FP64
  *       and for the reach-4 set, which runs tiles 2 and 3 only); seg = planes one workgroup
  *       marches; cpl is ignored.
  * 0 keeps the current value (for cpl: automatic). */
 scl_status scl_set_tiling(scl_lattice lat, int32_t strip, int32_t seg, int32_t cpl);
-/* Current tiling (2D: the strip in use, or -lanes with seg = rows per tile when one-shot tiles
- * are in use; 3D: the tile in use); cpl may be NULL. seg 0 means the automatic choice. */
+/* Current tiling (2D: the strip in use, or -lanes with seg = rows per tile and cpl = width in
+ * 64-column units when one-shot tiles are in use; 3D: the tile in use); cpl may be NULL. seg 0
+ * means the automatic choice. */
 scl_status scl_get_tiling(scl_lattice lat, int32_t* strip, int32_t* seg, int32_t* cpl);
 
 /* Autotuner: times the candidate tilings on this lattice (advancing it by the steps it

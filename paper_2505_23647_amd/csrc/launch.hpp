@@ -13,6 +13,7 @@ struct StepArgs {
   int strip;      // 2D: output lanes per workgroup in use
   int tile2;      // 2D: 0 = marching strips; 256 or 512 = one-shot 64 x tile_ty tiles, that many lanes
   int tile_ty;    // 2D tiles: rows per tile
+  int tile_tx;    // 2D tiles: columns per tile (64 or 128)
   int cpl;        // 2D: sites per lane
   int tile3;      // 3D: tile index in use (1: 64x4, 2: 64x8, 3: 32x8)
   int nitems;

@@ -41,18 +41,20 @@ template <class S, class M, bool SHIFT>
 hipError_t launch_tile2d(const StepArgs& a, const void* fin, void* fout) {
   const int per = (a.nitems + 7) / 8;
   const dim3 grid(8 * per);
-#define SCL_T2_CASE(SETV, TYV, NWV)                                                                   \
-  if (a.set == SETV && a.tile_ty == TYV && a.tile2 == 64 * NWV) {                                     \
-    hipLaunchKernelGGL((k_tile2d<S, M, SETV, TYV, NWV, SHIFT>), grid, dim3(64 * NWV), 0, a.stream,      \
+#define SCL_T2_CASE(SETV, TXV, TYV, NWV)                                                              \
+  if (a.set == SETV && a.tile_tx == TXV && a.tile_ty == TYV && a.tile2 == 64 * NWV) {                \
+    hipLaunchKernelGGL((k_tile2d<S, M, SETV, TXV, TYV, NWV, SHIFT>), grid, dim3(64 * NWV), 0, a.stream, \
                        (const S*)fin, (S*)fout, a.doms, a.items, a.nitems);                          \
     return hipGetLastError();                                                                        \
   }
-  SCL_T2_CASE(0, 8, 4) SCL_T2_CASE(0, 16, 4) SCL_T2_CASE(0, 24, 4) SCL_T2_CASE(0, 32, 4)
-  SCL_T2_CASE(0, 16, 8) SCL_T2_CASE(0, 24, 8) SCL_T2_CASE(0, 32, 8)
-  SCL_T2_CASE(1, 8, 4) SCL_T2_CASE(1, 16, 4) SCL_T2_CASE(1, 24, 4) SCL_T2_CASE(1, 32, 4)
-  SCL_T2_CASE(1, 16, 8) SCL_T2_CASE(1, 24, 8) SCL_T2_CASE(1, 32, 8)
-  SCL_T2_CASE(2, 8, 4) SCL_T2_CASE(2, 16, 4) SCL_T2_CASE(2, 24, 4) SCL_T2_CASE(2, 32, 4)
-  SCL_T2_CASE(2, 16, 8) SCL_T2_CASE(2, 24, 8) SCL_T2_CASE(2, 32, 8)
+#define SCL_T2_SET(SETV)                                                                                  \
+  SCL_T2_CASE(SETV, 64, 8, 4) SCL_T2_CASE(SETV, 64, 16, 4) SCL_T2_CASE(SETV, 64, 24, 4)                    \
+  SCL_T2_CASE(SETV, 64, 32, 4) SCL_T2_CASE(SETV, 64, 16, 8) SCL_T2_CASE(SETV, 64, 24, 8)                   \
+  SCL_T2_CASE(SETV, 64, 32, 8) SCL_T2_CASE(SETV, 128, 8, 4) SCL_T2_CASE(SETV, 128, 16, 4)                  \
+  SCL_T2_CASE(SETV, 128, 24, 4) SCL_T2_CASE(SETV, 128, 32, 4) SCL_T2_CASE(SETV, 128, 16, 8)                \
+  SCL_T2_CASE(SETV, 128, 24, 8) SCL_T2_CASE(SETV, 128, 32, 8)
+  SCL_T2_SET(0) SCL_T2_SET(1) SCL_T2_SET(2)
+#undef SCL_T2_SET
 #undef SCL_T2_CASE
   return hipErrorInvalidValue;
 }

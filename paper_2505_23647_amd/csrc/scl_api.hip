@@ -11,6 +11,7 @@
 #include <memory>
 #include <sstream>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "scl.h"
@@ -104,9 +105,11 @@ struct scl_lattice_s {
   // tiling
   int strip = 0, seg = 0;          // 2D: output lanes per workgroup, rows per item (0 = auto)
   int strip_eff = 256;             // 2D: output lanes per workgroup in use
-  int tile2 = 0, tile_ty = 16;     // 2D: one-shot 64-wide tiles requested (lanes, rows; 0 = none)
+  int tile2 = 0, tile_ty = 16;     // 2D: one-shot tiles requested (lanes, rows; 0 = none)
+  int tile_tx = 64;                // 2D: tile width requested (64 or 128 columns)
   int tile2_eff = 0;               // 2D: tiles in use (lanes; 0 = marching strips)
   int tile_ty_eff = 16;            // 2D: rows per tile in use
+  int tile_tx_eff = 64;            // 2D: tile width in use
   bool march_only = false;         // 2D: tiles switched off (the adjoint's recording pass)
   int cpl_req = 0;                 // 2D: sites per lane requested (0 = auto)
   int cpl = 1;                     // 2D: sites per lane in use
@@ -234,32 +237,42 @@ int auto_strip(const scl_lattice_s* L, int cpl) {
 scl_status build_items(scl_lattice_s* L) {
   std::vector<WorkItem> items;
   // 2D tiles: as requested, or automatically (no tiling asked for, shell sets of reach 1 and 2)
-  //  * for FP64 storage: measured on MI355X, 4096^2, 24 vectors, 256-lane tiles of 64 x 16
-  //    sites take 0.444 ms per step against 0.507 ms for the best marching strips (for 4- and
-  //    2-byte storage the strips are as fast or faster there);
+  //  * for FP64 storage: measured on MI355X, 4096^2, 24 vectors, 256-lane tiles of 128 x 8
+  //    sites take 0.437 ms per step (64 x 16: 0.444) against 0.507 ms for the best marching
+  //    strips;
   //  * for domains narrow enough that the automatic strips leave more than 1/8 of their lanes
   //    idle: the 64 droplet and bubble domains of sides 64..544 run 48.5 GLUPS on 512-lane
-  //    tiles of 64 x 16 sites against 43.2 on 256-lane strips (30% idle lanes), FP32 shifted.
+  //    tiles of 64 x 16 sites against 43.2 on 256-lane strips (30% idle lanes), FP32 shifted;
+  //  * for FP16 storage: 256-lane tiles of 128 x 16 sites, 0.148 ms per step against 0.157 for
+  //    the best marching strips (for FP32 storage the strips stay faster: 0.234 against 0.244
+  //    for the best tiles).
   L->tile2_eff = 0;
   if (L->d == 2 && !L->march_only) {
     const bool asked = L->strip || L->seg || L->cpl_req;
     if (L->tile2) {
       L->tile2_eff = L->tile2;
       L->tile_ty_eff = L->tile_ty;
+      L->tile_tx_eff = L->tile_tx;
     } else if (!asked && L->set != 2 && planes_fit_tiles(L)) {
       if (L->prec == SCL_FP64) {
         L->tile2_eff = 256;
-        L->tile_ty_eff = 16;
+        L->tile_ty_eff = 8;
+        L->tile_tx_eff = 128;
       } else if (strip_idle(L, auto_strip(L, 1), 1) * 8 > L->cells) {
         L->tile2_eff = 512;
         L->tile_ty_eff = 16;
+        L->tile_tx_eff = 64;
+      } else if (L->prec == SCL_FP16S_FP32) {
+        L->tile2_eff = 256;
+        L->tile_ty_eff = 16;
+        L->tile_tx_eff = 128;
       }
     }
   }
   if (L->tile2_eff) {
     L->cpl = 1;
-    // one-shot tiles of 64 x tile_ty sites. Order: within each domain, column blocks of CB
-    // tiles, each taken row by row. Each XCD takes a contiguous eighth of the list, and the
+    // one-shot tiles of tile_tx x tile_ty sites. Order: within each domain, column blocks of
+    // 64 CB sites, each taken row by row. Each XCD takes a contiguous eighth of the list, and the
     // tile above a tile was loaded a block's width of tiles earlier, so the rim rows two tiles
     // share still sit in that XCD's L2. Row-major order over a 4096-wide domain (64 tiles per
     // row) let 256-lane FP32 tiles fetch 1.39x the populations they need. Measured on MI355X
@@ -270,7 +283,7 @@ scl_status build_items(scl_lattice_s* L) {
     for (int k = 0; k < L->ndom; ++k)
       for (int b0 = 0; b0 < L->nx[k]; b0 += 64 * CB)
         for (int y0 = 0; y0 < L->ny[k]; y0 += L->tile_ty_eff)
-          for (int x0 = b0; x0 < std::min(b0 + 64 * CB, L->nx[k]); x0 += 64) {
+          for (int x0 = b0; x0 < std::min(b0 + 64 * CB, L->nx[k]); x0 += L->tile_tx_eff) {
             WorkItem w{};
             w.dom = k; w.x0 = x0; w.y0 = y0; w.y1 = std::min(y0 + L->tile_ty_eff, L->ny[k]);
             w.z0 = 0; w.z1 = 1; w.dir = 1;
@@ -393,6 +406,7 @@ StepArgs step_args(const scl_lattice_s* L) {
   a.strip = L->strip_eff;
   a.tile2 = L->tile2_eff;
   a.tile_ty = L->tile_ty_eff;
+  a.tile_tx = L->tile_tx_eff;
   a.cpl = L->cpl;
   a.tile3 = L->tile3_eff;
   a.nitems = L->nitems;
@@ -1228,14 +1242,16 @@ scl_status scl_flat_observables(scl_lattice L, const double* bulk, double* out) 
 scl_status scl_set_tiling(scl_lattice L, int32_t strip, int32_t seg, int32_t cpl) {
   if (!L || seg < 0 || cpl < 0 || (strip < 0 && L->d != 2)) return fail(SCL_E_INVALID, "bad tiling");
   if (L->d == 2 && strip < 0) {
-    // one-shot tiles: -strip lanes (256 or 512), seg rows per tile
-    const int nt = -strip, ty = seg ? seg : 16;
+    // one-shot tiles: -strip lanes (256 or 512), seg rows per tile, cpl 64-column units of width
+    const int nt = -strip, ty = seg ? seg : 16, tx = cpl == 2 ? 128 : 64;
     if (nt != 256 && nt != 512) return fail(SCL_E_INVALID, "2D tiles run 256 or 512 lanes (strip -256 or -512)");
     if (ty != 8 && ty != 16 && ty != 24 && ty != 32) return fail(SCL_E_INVALID, "2D tiles are 8, 16, 24 or 32 rows high");
+    if (cpl > 2) return fail(SCL_E_INVALID, "2D tiles are 64 (cpl 0 or 1) or 128 (cpl 2) columns wide");
     if (nt == 512 && ty == 8) return fail(SCL_E_UNSUPPORTED, "512-lane tiles are 16, 24 or 32 rows high");
     if (!planes_fit_tiles(L)) return fail(SCL_E_UNSUPPORTED, "2D tiles need every domain's population plane under 2 GiB");
     L->tile2 = nt;
     L->tile_ty = ty;
+    L->tile_tx = tx;
     L->dirty_items = true;
     drop_graph(L);
     return SCL_OK;
@@ -1275,7 +1291,7 @@ scl_status scl_get_tiling(scl_lattice L, int32_t* strip, int32_t* seg, int32_t* 
   }
   *strip = L->d == 2 ? (L->tile2_eff ? -L->tile2_eff : L->strip_eff) : L->tile3_eff;
   *seg = L->d == 2 ? (L->tile2_eff ? L->tile_ty_eff : L->seg) : L->seg3;
-  if (cpl) *cpl = L->d == 2 ? L->cpl : 1;
+  if (cpl) *cpl = L->d == 2 ? (L->tile2_eff ? L->tile_tx_eff / 64 : L->cpl) : 1;
   return SCL_OK;
 }
 
@@ -1304,33 +1320,34 @@ scl_status scl_tune(scl_lattice L, const char* cache_path) {
     while (std::getline(in, line)) {
       const size_t bar = line.rfind('|');
       if (bar == std::string::npos || line.substr(0, bar) != ks) continue;
-      int a = 0, b = 0;
-      if (std::sscanf(line.c_str() + bar + 1, "%d %d", &a, &b) == 2) return scl_set_tiling(L, a, b, 0);
+      int a = 0, b = 0, c = 0;
+      if (std::sscanf(line.c_str() + bar + 1, "%d %d %d", &a, &b, &c) >= 2) return scl_set_tiling(L, a, b, c);
     }
   }
-  std::vector<std::pair<int, int>> cands;
+  std::vector<std::array<int, 3>> cands;  // (strip, seg, cpl)
   if (L->d == 2) {
     for (int st : {64, 128, 256, 512}) {
       if ((st == 64 || st == 512) && L->set == 2) continue;
-      for (int sg : {8, 16, 32, 64, 128}) cands.push_back({st, sg});
+      for (int sg : {8, 16, 32, 64, 128}) cands.push_back({st, sg, 0});
     }
-    if (planes_fit_tiles(L)) {
-      for (int ty : {8, 16, 24, 32}) cands.push_back({-256, ty});
-      for (int ty : {16, 24, 32}) cands.push_back({-512, ty});
-    }
+    if (planes_fit_tiles(L))
+      for (int w : {1, 2}) {
+        for (int ty : {8, 16, 24, 32}) cands.push_back({-256, ty, w});
+        for (int ty : {16, 24, 32}) cands.push_back({-512, ty, w});
+      }
   } else {
     for (int t : {1, 2, 3, 4}) {
       if ((t == 1 || t == 4) && L->set == 2) continue;
-      for (int sg : {8, 16, 32, 64}) cands.push_back({t, sg});
+      for (int sg : {8, 16, 32, 64}) cands.push_back({t, sg, 0});
     }
   }
   const int saved_graph = L->graph_k;
   L->graph_k = 0;
   double best = 1e30;
-  std::pair<int, int> bc = cands[0];
+  std::array<int, 3> bc = cands[0];
   const int reps = 4;
   for (auto c : cands) {
-    s = scl_set_tiling(L, c.first, c.second, 0);
+    s = scl_set_tiling(L, c[0], c[1], c[2]);
     if (s != SCL_OK) return s;
     double ms = 0;
     s = scl_step_timed(L, 2, &ms);  // warm-up (and item upload)
@@ -1340,11 +1357,11 @@ scl_status scl_tune(scl_lattice L, const char* cache_path) {
     if (ms < best) { best = ms; bc = c; }
   }
   L->graph_k = saved_graph;
-  s = scl_set_tiling(L, bc.first, bc.second, 0);
+  s = scl_set_tiling(L, bc[0], bc[1], bc[2]);
   if (s != SCL_OK) return s;
   if (cache_path) {
     std::ofstream o(cache_path, std::ios::app);
-    o << ks << "|" << bc.first << " " << bc.second << "\n";
+    o << ks << "|" << bc[0] << " " << bc[1] << " " << bc[2] << "\n";
   }
   return SCL_OK;
 }

@@ -1,8 +1,9 @@
 // Fused D2Q9 Shan-Chen step over independent tiles: pull-stream, moments, psi, wide-stencil
 // force, BGK + Guo collision, one workgroup per tile of 64 x TY output sites, no march.
 //
-// A workgroup of NW waves owns the output sites [x0, x0 + 64) x [y0, y0 + TY) of one domain.
-// Lane l of wave w holds the sites (x0 + l, y0 + w + NW k), k < TY / NW: it pulls their nine
+// A workgroup of NW waves owns the output sites [x0, x0 + TX) x [y0, y0 + TY) of one domain
+// (TX = 64 or 128: one or two waves per tile row). Its lanes form RG = 64 NW / TX row groups;
+// lane l of row group g holds the sites (x0 + l, y0 + g + RG k), k < TY / RG: it pulls their nine
 // populations (f_i(x, t) = f*_i(x - xi_i, t - 1)) into registers. The psi of every site the
 // stencil reaches, the tile plus a rim of R sites, goes to LDS: the tile's own sites from the
 // populations just loaded, the rim's from a second set of pulls (2R rim rows of 64 sites split
@@ -17,7 +18,7 @@
 
 namespace scl {
 
-template <class S, class M, int SET, int TY, int NW, bool SHIFT>
+template <class S, class M, int SET, int TX, int TY, int NW, bool SHIFT>
 __global__ void __launch_bounds__(64 * NW)
 k_tile2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restrict__ doms,
          const WorkItem* __restrict__ items, int nitems) {
@@ -25,15 +26,15 @@ k_tile2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
   using SH = Shells<2, SET>;
   constexpr int Q = V::Q;
   constexpr int R = SH::R;
-  constexpr int TX = 64;
   constexpr int NT = 64 * NW;
   constexpr int LW = TX + 2 * R;            // LDS row: the tile's columns plus R on each side
   constexpr int LH = TY + 2 * R;            // LDS rows
-  constexpr int KI = TY / NW;               // tile rows per lane
-  constexpr int KH = (2 * R + NW - 1) / NW; // rim rows (main columns) per wave
+  constexpr int RG = NT / TX;               // tile rows taken at once (TX lanes each)
+  constexpr int KI = TY / RG;               // tile rows per lane
+  constexpr int KH = (2 * R + RG - 1) / RG; // rim rows (main columns) per row group
   constexpr int NSIDE = LH * 2 * R;         // side sites: R columns on each side of every LDS row
   constexpr int KS = (NSIDE + NT - 1) / NT;
-  static_assert(TY % NW == 0, "tile rows must split evenly over the waves");
+  static_assert(TX % 64 == 0 && NT % TX == 0 && TY % RG == 0, "tile rows must split evenly over the row groups");
   constexpr uint32_t OFF = 0x80000000u;     // byte offset past any buffer: access dropped
 
   __shared__ M psis[LH * LW];
@@ -53,8 +54,8 @@ k_tile2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
   const M eps = M(dm.eps), inv_eps = M(dm.inv_eps), rho0 = M(dm.rho0);
   const int kind = dm.psi_kind;
 
-  const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int lane = (int)threadIdx.x % TX;                                 // column in the tile
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x / TX);   // row group (wave-uniform)
   const int x0 = it.x0, y0 = it.y0;
   const int xe = min(x0 + TX, nx), ye = it.y1;  // tile end (cut by the domain's edge)
   const int x = x0 + lane;
@@ -85,12 +86,12 @@ k_tile2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
   // ---- 1. pulls: the lane's tile sites, its rim-row sites, its side sites
   M fi[KI][Q];
 #pragma unroll
-  for (int k = 0; k < KI; ++k) pull_row(y0 + w + NW * k, y0 + w + NW * k < ye, fi[k]);
+  for (int k = 0; k < KI; ++k) pull_row(y0 + w + RG * k, y0 + w + RG * k < ye, fi[k]);
 
   M fh[KH][Q];
 #pragma unroll
   for (int k = 0; k < KH; ++k) {
-    const int h = w + NW * k;  // rim row: 0 .. R-1 above the tile, R .. 2R-1 below it
+    const int h = w + RG * k;  // rim row: 0 .. R-1 above the tile, R .. 2R-1 below it
     const int y = h < R ? y0 - R + h : ye + (h - R);
     pull_row(y, h < 2 * R, fh[k]);
   }
@@ -134,14 +135,14 @@ k_tile2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
   M ssum[KI];  // the tile sites' sums, reused by the collision
 #pragma unroll
   for (int k = 0; k < KI; ++k) {
-    const int ly = w + NW * k + R;
+    const int ly = w + RG * k + R;
     ssum[k] = vsum(fi[k]);
     const M p = psi_of(ssum[k]);
-    if (xin && y0 + w + NW * k < ye) psis[ly * LW + lane + R] = p;
+    if (xin && y0 + w + RG * k < ye) psis[ly * LW + lane + R] = p;
   }
 #pragma unroll
   for (int k = 0; k < KH; ++k) {
-    const int h = w + NW * k;
+    const int h = w + RG * k;
     const int ly = h < R ? h : (ye - y0) + R + (h - R);
     const M p = psi_of(vsum(fh[k]));
     if (xin && h < 2 * R) psis[ly * LW + lane + R] = p;
@@ -156,8 +157,8 @@ k_tile2d(const S* __restrict__ fin, S* __restrict__ fout, const DomDev* __restri
   // ---- 3. force, collision and store of the lane's tile sites
 #pragma unroll
   for (int k = 0; k < KI; ++k) {
-    const int y = y0 + w + NW * k;
-    const int ly = w + NW * k + R;
+    const int y = y0 + w + RG * k;
+    const int ly = w + RG * k + R;
     const M* c0 = psis + ly * LW + lane + R;
     const M psic = c0[0];
     M dxs[SH::NS], dys[SH::NS];

@@ -19,7 +19,8 @@ from tests.gpu_helpers import E4_2D, E8_2D, coupling, family2d_weights, oracle_r
 pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-12
-TILES = [(-256, 8), (-256, 16), (-256, 24), (-256, 32), (-512, 16), (-512, 24), (-512, 32)]
+TILES = [(-256, 8, 1), (-256, 16, 1), (-256, 24, 1), (-256, 32, 1), (-512, 16, 1), (-512, 24, 1), (-512, 32, 1),
+         (-256, 8, 2), (-256, 16, 2), (-512, 16, 2), (-512, 32, 2)]
 REACH4 = list(stencil.TOLMAN_SHELLS_2D)
 
 
@@ -30,17 +31,17 @@ def _lat(dims, prec, G, codes, W, n0, tiling, tau=1.0):
     return lat.init_density(n0)
 
 
-@pytest.mark.parametrize("strip,seg", TILES)
-def test_tiles_ragged_fp64_vs_oracle(strip, seg):
+@pytest.mark.parametrize("strip,seg,width", TILES)
+def test_tiles_ragged_fp64_vs_oracle(strip, seg, width):
     """250 x 190 (3 full tiles + 58 columns; rows not a multiple of any tile height), 24-vector
     stencil, spinodal start, 150 steps."""
-    say(f"case: tiles {strip}x{seg} ragged 250x190 fp64")
+    say(f"case: tiles {strip}x{seg} width {64 * width} ragged 250x190 fp64")
     G = coupling(0.2)
     W = family2d_weights(0.55, 0.55 ** 2 * (16 / 105) / (4 / 7) ** 2)
     dims = (250, 190)
     n0 = synth.uniform(dims, 0.9, 1.1, seed=1)
-    lat = _lat([dims], SCL_FP64, G, E8_2D[0], W, n0, (strip, seg, 0))
-    assert tuple(lat.get_tiling()) == (strip, seg, 1)
+    lat = _lat([dims], SCL_FP64, G, E8_2D[0], W, n0, (strip, seg, width))
+    assert tuple(lat.get_tiling()) == (strip, seg, width)
     lat.step(150)
     ora, _ = oracle_run(dims, 1.0, G, E8_2D[0], W, n0, 150)
     e = rel_err(lat.domain_populations(0)[perm_to_oracle(lat.xi, 2)], ora.f)
@@ -57,7 +58,7 @@ def test_tiles_small_and_degenerate_fp64(dims):
     W = family2d_weights(0.5, 0.1)
     n0 = synth.uniform(dims, 0.95, 1.05, seed=3)
     ora, _ = oracle_run(dims, 0.9, G, E8_2D[0], W, n0, 40)
-    for tiling in ((-256, 8, 0), (-512, 16, 0)):
+    for tiling in ((-256, 8, 0), (-512, 16, 0), (-256, 8, 2)):
         lat = _lat([dims], SCL_FP64, G, E8_2D[0], W, n0, tiling, tau=0.9)
         lat.step(40)
         e = rel_err(lat.domain_populations(0)[perm_to_oracle(lat.xi, 2)], ora.f)
@@ -84,10 +85,10 @@ def test_tiles_bitwise_equal_marching(prec, shells):
     ref.step(40)
     pref = ref.populations()
     assert np.all(np.isfinite(pref))
-    for strip, seg in ((-256, 8), (-256, 24), (-512, 32)):
-        lat = _lat(dims, prec, G, codes, W, n0, (strip, seg, 0))
+    for strip, seg, width in ((-256, 8, 1), (-256, 24, 1), (-512, 32, 1), (-256, 8, 2), (-256, 16, 2), (-512, 24, 2)):
+        lat = _lat(dims, prec, G, codes, W, n0, (strip, seg, width))
         lat.step(40)
-        assert np.array_equal(lat.populations(), pref), (strip, seg)
+        assert np.array_equal(lat.populations(), pref), (strip, seg, width)
 
 
 def test_tiles_graph_replay():
@@ -108,13 +109,14 @@ def test_tiles_graph_replay():
 
 
 def test_tiles_selection_and_validation():
-    """FP64 lattices with the reach-1 and reach-2 sets step through 256-lane 64 x 16 tiles unless
-    a tiling is requested, and so do narrow batched domains through 512-lane 64 x 16 tiles;
-    other lattices march; bad tile shapes are rejected."""
+    """FP64 lattices with the reach-1 and reach-2 sets step through 256-lane 128 x 8 tiles unless
+    a tiling is requested, narrow batched domains through 512-lane 64 x 16 tiles and FP16
+    lattices through 256-lane 128 x 16 tiles; FP32 lattices march; bad tile shapes are
+    rejected."""
     say("case: tile selection and validation")
     G = coupling(0.2)
     lat = Lattice([(128, 96)], SCL_FP64).set_physics(1.0, G).set_stencil(*E8_2D)
-    assert tuple(lat.get_tiling()) == (-256, 16, 1)
+    assert tuple(lat.get_tiling()) == (-256, 8, 2)
     lat.set_tiling(128, 0, 0)
     assert lat.get_tiling()[0] == 128
     lat.set_tiling(-512, 24, 0)
@@ -123,12 +125,14 @@ def test_tiles_selection_and_validation():
     assert l4.get_tiling()[0] > 0
     l32 = Lattice([(128, 96)], SCL_FP32_SHIFTED).set_physics(1.0, G).set_stencil(*E8_2D)
     assert l32.get_tiling()[0] > 0
+    l16 = Lattice([(512, 512)], SCL_FP16S_FP32).set_physics(1.0, G).set_stencil(*E8_2D)
+    assert tuple(l16.get_tiling()) == (-256, 16, 2)
     # narrow batched domains: 256-lane strips would leave 48% of their lanes idle
     narrow = Lattice([(64, 64), (100, 100), (544, 544)], SCL_FP32_SHIFTED).set_physics(1.0, G).set_stencil(*E8_2D)
     assert tuple(narrow.get_tiling()) == (-512, 16, 1)
     wide = Lattice([(256, 256)] * 4, SCL_FP32_SHIFTED).set_physics(1.0, G).set_stencil(*E8_2D)
     assert wide.get_tiling()[0] == 256
-    for bad in ((-128, 16, 0), (-256, 12, 0), (-512, 8, 0), (-64, 0, 0)):
+    for bad in ((-128, 16, 0), (-256, 12, 0), (-512, 8, 0), (-64, 0, 0), (-256, 16, 3)):
         with pytest.raises(SclError):
             lat.set_tiling(*bad)
     with pytest.raises(SclError):
