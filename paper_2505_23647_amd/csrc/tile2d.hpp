@@ -1,13 +1,13 @@
 // Fused D2Q9 Shan-Chen step over independent tiles: pull-stream, moments, psi, wide-stencil
-// force, BGK + Guo collision, one workgroup per tile of 64 x TY output sites, no march.
+// force, BGK + Guo collision, one workgroup per tile of TX x TY output sites, no march.
 //
 // A workgroup of NW waves owns the output sites [x0, x0 + TX) x [y0, y0 + TY) of one domain
 // (TX = 64 or 128: one or two waves per tile row). Its lanes form RG = 64 NW / TX row groups;
 // lane l of row group g holds the sites (x0 + l, y0 + g + RG k), k < TY / RG: it pulls their nine
 // populations (f_i(x, t) = f*_i(x - xi_i, t - 1)) into registers. The psi of every site the
 // stencil reaches, the tile plus a rim of R sites, goes to LDS: the tile's own sites from the
-// populations just loaded, the rim's from a second set of pulls (2R rim rows of 64 sites split
-// over the waves, and the (TY + 2R) x 2R side sites spread over all lanes). After one barrier
+// populations just loaded, the rim's from a second set of pulls (2R rim rows of TX sites split
+// over the row groups, and the (TY + 2R) x 2R side sites spread over all lanes). After one barrier
 // each lane evaluates the force of eq. (sc_f) from LDS, collides (eqs. lbm, omega_i, f_eq,
 // GuoForcing) and stores its sites. All of a tile's loads are issued at once, and the grid holds
 // one workgroup per tile, so the chip keeps many independent loads in flight and consecutive
